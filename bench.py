@@ -1,0 +1,225 @@
+"""Throughput of the batched Whittaker-Henderson smoother on one MI355X.
+
+One step = one forward solve (``whs_solve``) plus one adjoint
+(``whs_backward``) over the whole batch, inputs resident in HBM.  The
+default workload is the heteroscedastic one: P = 65,536 series, T = 3288
+daily steps (2016-2024), order d = 2, one band, one smoothing weight per
+difference row (a GP field in log10), FP32 storage with FP64 arithmetic.
+
+Prints one JSON line.  ``roofline`` covers the dominant kernel (the
+adjoint), timed with HIP events on the stream it runs on; ``cpu_baseline``
+times the FP64 CPU oracle on a bounded sample of the same inputs.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "series/sec (T=3288,d=2,fwd+bwd) and % of HBM roofline; held-out RMSE vs plain"
+PEAK_HBM_GBS = 8000.0
+
+
+def alg_bytes(T: int, d: int, C: int, esz: int, per_diff: bool):
+    """Algorithmic HBM bytes per series: every API tensor once per pass at its dtype."""
+    lam = esz * (T - d) if per_diff else esz
+    fwd = esz * T * C + T + lam + esz * T * C                        # x, w, lambda in; z out
+    bwd = esz * T * C + T + lam + esz * T * C + esz * T * C + lam    # g, w, lambda, z in; grad_x, grad_lambda out
+    return fwd, bwd
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2604_00048_amd", "csrc")
+    for dirpath, _, files in sorted(os.walk(csrc)):
+        for f in sorted(files):
+            if f.endswith((".hip", ".h")):
+                with open(os.path.join(dirpath, f), "rb") as fh:
+                    h.update(f.encode())
+                    h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    if none exists for this kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    e = rec.get(f"{kernel}|{workload}")
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def _cpu_worker(args):
+    import numpy as np
+    from oracle import whs_ref as R
+    x, w, lam, g, d = args
+    z, _ = R.solve_band(x, w, lam, d)
+    R.vjp(x, w, lam, d, g, z=z)
+    return x.shape[0]
+
+
+def cpu_baseline(pk, d: int, n_sample: int, workers: int):
+    """Time the FP64 oracle (forward + adjoint) on ``n_sample`` series of the same
+    inputs, split over ``workers`` processes."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    idx = torch.arange(n_sample)
+    b = pk.series(idx)
+    x = b.x.numpy()[:, :, 0]
+    w = b.w.numpy()
+    lam = b.lam.numpy()
+    g = np.random.default_rng(0).normal(size=x.shape)
+    chunks = np.array_split(np.arange(n_sample), workers)
+    jobs = [(x[c], w[c], lam[c], g[c], d) for c in chunks if len(c)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(len(jobs)) as pool:
+        pool.map(_cpu_worker, [(j[0][:2], j[1][:2], j[2][:2], j[3][:2], d) for j in jobs])  # warm imports
+        t0 = time.perf_counter()
+        done = sum(pool.map(_cpu_worker, jobs))
+        dt = time.perf_counter() - t0
+    return done / dt, dt, len(jobs)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--P", type=int, default=65536)
+    ap.add_argument("--T", type=int, default=3288)
+    ap.add_argument("--interleave", type=int, default=64)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (pixels shard across GPUs "
+                                   "with no exchange, see the design notes)"}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2604_00048_amd import synth, whs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    whs.lib()
+    d, S, P, T = 2, args.interleave, args.P, args.T
+    t_gen = time.perf_counter()
+    pk = synth.generate_packed("heteroscedastic", P, S=S, dtype=torch.float32, device=dev, chunk=8192, T=T)
+    g = torch.randn(pk.x.shape, generator=torch.Generator(device=dev).manual_seed(7), device=dev,
+                    dtype=torch.float32)
+    z = torch.empty_like(pk.x)
+    gx = torch.empty_like(pk.x)
+    gl = torch.empty_like(pk.lam)
+    info = torch.empty(P, dtype=torch.int32, device=dev)
+    desc = whs.make_desc(P, T, d, 1, S, whs.WHS_F32, whs.WHS_LAMBDA_PER_DIFF)
+    ws = torch.empty(whs.workspace_bytes(desc), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    print(f"# inputs generated in {t_gen:.1f}s; workspace {ws.numel() / 1e6:.1f} MB", file=sys.stderr, flush=True)
+
+    def step():
+        whs.whs_solve(pk.x, pk.w, pk.lam, d, P, z=z, info=info, workspace=ws)
+        whs.whs_backward(pk.w, pk.lam, z, g, d, P, grad_x=gx, grad_lambda=gl, info=info, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for k in range(K):
+        ev[k][0].record()
+        whs.whs_solve(pk.x, pk.w, pk.lam, d, P, z=z, info=info, workspace=ws)
+        ev[k][1].record()
+        whs.whs_backward(pk.w, pk.lam, z, g, d, P, grad_x=gx, grad_lambda=gl, info=info, workspace=ws)
+        ev[k][2].record()
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(end)
+    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    bwd_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+    ms_step = total_ms / K
+    n_fail = int((info != 0).sum().item())
+
+    fb, bb = alg_bytes(T, d, 1, 4, True)
+    bwd_gbs = bb * P / (bwd_ms * 1e-3) / 1e9
+    fwd_gbs = fb * P / (fwd_ms * 1e-3) / 1e9
+    step_gbs = (fb + bb) * P / (ms_step * 1e-3) / 1e9
+    workload = f"heteroscedastic P={P} T={T} d={d} C=1"
+    traffic = measured_traffic("whs_backward", workload)
+    out = {
+        "metric": METRIC,
+        "value": P / (ms_step * 1e-3),
+        "unit": "series/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "heteroscedastic smoother fwd+bwd: P=65536 series, T=3288 daily steps, d=2, C=1 band, "
+                        "per-difference lambda (log10 GP field), FP32 storage / FP64 arithmetic",
+            "P": P, "T": T, "d": d, "C": 1, "storage": "f32", "interleave": S,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "whs_backward",
+            "achieved": bwd_gbs,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": bwd_gbs / PEAK_HBM_GBS,
+            "traffic": traffic,
+            "alg_bytes_per_series": bb,
+            "ms_per_launch": bwd_ms,
+        },
+        "kernels": {
+            "whs_solve": {"ms": fwd_ms, "alg_GBps": fwd_gbs, "frac": fwd_gbs / PEAK_HBM_GBS,
+                          "alg_bytes_per_series": fb},
+            "whs_backward": {"ms": bwd_ms, "alg_GBps": bwd_gbs, "frac": bwd_gbs / PEAK_HBM_GBS},
+            "step": {"ms": ms_step, "alg_GBps": step_gbs, "frac": step_gbs / PEAK_HBM_GBS},
+        },
+        "failed_series": n_fail,
+        "wall_s_timed": wall,
+    }
+    if not args.no_cpu_baseline:
+        n = min(args.cpu_sample, P)
+        workers = min(16, os.cpu_count() or 1, n)
+        rate, secs, used = cpu_baseline(pk, d, n, workers)
+        out["cpu_baseline"] = {
+            "value": rate, "unit": "series/s", "cores": used, "kind": "oracle",
+            "sample": f"{n} of the {P} series (first ones), FP64 numpy banded LDL^T forward + adjoint, "
+                      f"{used} processes, {secs:.1f} s",
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

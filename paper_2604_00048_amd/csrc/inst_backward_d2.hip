@@ -1,0 +1,6 @@
+// Instantiations of the two-sweep kernels: backward, order d = 2.
+#include "whs_two_sweep.h"
+
+namespace whs {
+hipError_t run_backward_d2(const LaunchDesc& L, hipStream_t stream) { return run_mode_d<2, Mode::Backward>(L, stream); }
+}  // namespace whs

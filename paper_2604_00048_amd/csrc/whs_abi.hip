@@ -1,0 +1,134 @@
+// C-ABI entry points of libwhs: argument validation and dispatch.
+#include <hip/hip_runtime.h>
+
+#include "whs.h"
+#include "whs_kernels.h"
+
+namespace {
+
+constexpr int kMaxD = 4;
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int check_desc(const whs_desc* d) {
+  if (!d) return WHS_ERR_ARG;
+  if (d->n_series < 0 || d->T < 1 || d->d < 1 || d->n_rhs < 1 || d->interleave < 1) return WHS_ERR_ARG;
+  if (d->dtype != WHS_F32 && d->dtype != WHS_F64) return WHS_ERR_ARG;
+  if (d->lambda_kind != WHS_LAMBDA_SCALAR && d->lambda_kind != WHS_LAMBDA_PER_DIFF) return WHS_ERR_ARG;
+  if (d->d > kMaxD) return WHS_ERR_UNSUPPORTED;
+  if (d->T <= d->d) return WHS_ERR_ARG;
+  // grid of ceil(P/256) blocks must fit one launch dimension
+  if (d->n_series > (int64_t)0x7fffffff * 256) return WHS_ERR_UNSUPPORTED;
+  return WHS_OK;
+}
+
+size_t elem(const whs_desc* d) { return d->dtype == WHS_F64 ? 8 : 4; }
+
+whs::LaunchDesc make_launch(const whs_desc* d) {
+  whs::LaunchDesc L{};
+  L.P = d->n_series;
+  L.T = d->T;
+  L.D = d->d;
+  L.C = d->n_rhs;
+  L.S = d->interleave;
+  L.f64 = d->dtype == WHS_F64;
+  L.perdiff = d->lambda_kind == WHS_LAMBDA_PER_DIFF;
+  return L;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? WHS_OK : WHS_ERR_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+const char* whs_status_str(int status) {
+  switch (status) {
+    case WHS_OK: return "ok";
+    case WHS_ERR_ARG: return "invalid argument (descriptor, null or misaligned pointer)";
+    case WHS_ERR_UNSUPPORTED: return "unsupported configuration (order d > 4 or too many series)";
+    case WHS_ERR_HIP: return "HIP runtime or launch error";
+    case WHS_ERR_WORKSPACE: return "workspace missing or smaller than whs_workspace_bytes()";
+    default: return "unknown status";
+  }
+}
+
+int whs_version(void) { return 100; }
+
+size_t whs_workspace_bytes(const whs_desc* desc) {
+  if (check_desc(desc) != WHS_OK || desc->n_series == 0) return 0;
+  return whs::checkpoint_bytes(desc->n_series, desc->interleave, desc->T, desc->d, desc->n_rhs);
+}
+
+size_t whs_factor_bytes(const whs_desc* desc) {
+  if (check_desc(desc) != WHS_OK) return 0;
+  const int64_t nb = (desc->n_series + desc->interleave - 1) / desc->interleave;
+  return (size_t)nb * desc->interleave * (desc->d + 1) * (size_t)desc->T * sizeof(double);
+}
+
+int whs_factor(const whs_desc* desc, const uint8_t* w, const void* lambda, double* factor, int32_t* info,
+               void* stream) {
+  int st = check_desc(desc);
+  if (st != WHS_OK) return st;
+  if (desc->n_series == 0) return WHS_OK;
+  if (!w || !lambda || !factor) return WHS_ERR_ARG;
+  if (!aligned(lambda, elem(desc)) || !aligned(factor, 8) || !aligned(info, 4)) return WHS_ERR_ARG;
+  whs::LaunchDesc L = make_launch(desc);
+  L.w = w;
+  L.lam = lambda;
+  L.fac = factor;
+  L.info = info;
+  return hip_status(whs::launch_factor(L, static_cast<hipStream_t>(stream)));
+}
+
+int whs_solve(const whs_desc* desc, const uint8_t* w, const void* lambda, const double* factor, const void* x,
+              void* z, int32_t* info, void* workspace, size_t workspace_bytes, void* stream) {
+  int st = check_desc(desc);
+  if (st != WHS_OK) return st;
+  if (desc->n_series == 0) return WHS_OK;
+  if (!w || !x || !z) return WHS_ERR_ARG;
+  if (!factor && !lambda) return WHS_ERR_ARG;
+  const size_t e = elem(desc);
+  if (!aligned(x, e) || !aligned(z, e) || (lambda && !aligned(lambda, e)) || !aligned(factor, 8) ||
+      !aligned(info, 4))
+    return WHS_ERR_ARG;
+  if (!workspace || workspace_bytes < whs_workspace_bytes(desc) || !aligned(workspace, 8)) return WHS_ERR_WORKSPACE;
+  whs::LaunchDesc L = make_launch(desc);
+  L.w = w;
+  L.lam = lambda;
+  L.fac = factor;
+  L.rhs = x;
+  L.out = z;
+  L.info = info;
+  L.ws = static_cast<double*>(workspace);
+  return hip_status(whs::launch_solve(L, static_cast<hipStream_t>(stream)));
+}
+
+int whs_backward(const whs_desc* desc, const uint8_t* w, const void* lambda, const double* factor, const void* z,
+                 const void* g, void* grad_x, void* grad_lambda, int32_t* info, void* workspace,
+                 size_t workspace_bytes, void* stream) {
+  int st = check_desc(desc);
+  if (st != WHS_OK) return st;
+  if (desc->n_series == 0) return WHS_OK;
+  if (!w || !z || !g) return WHS_ERR_ARG;
+  if (!factor && !lambda) return WHS_ERR_ARG;
+  const size_t e = elem(desc);
+  if (!aligned(z, e) || !aligned(g, e) || !aligned(grad_x, e) || !aligned(grad_lambda, e) ||
+      (lambda && !aligned(lambda, e)) || !aligned(factor, 8) || !aligned(info, 4))
+    return WHS_ERR_ARG;
+  if (!workspace || workspace_bytes < whs_workspace_bytes(desc) || !aligned(workspace, 8)) return WHS_ERR_WORKSPACE;
+  if (!grad_x && !grad_lambda && !info) return WHS_OK;
+  whs::LaunchDesc L = make_launch(desc);
+  L.w = w;
+  L.lam = lambda;
+  L.fac = factor;
+  L.rhs = g;
+  L.zin = z;
+  L.out = grad_x;
+  L.glam = grad_lambda;
+  L.info = info;
+  L.ws = static_cast<double*>(workspace);
+  return hip_status(whs::launch_backward(L, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,56 @@
+// Dispatch of the two-sweep kernels over the difference order, and sizes.
+#include <hip/hip_runtime.h>
+
+#include "whs_two_sweep.h"
+
+namespace whs {
+
+hipError_t run_solve_d1(const LaunchDesc&, hipStream_t);
+hipError_t run_solve_d2(const LaunchDesc&, hipStream_t);
+hipError_t run_solve_d3(const LaunchDesc&, hipStream_t);
+hipError_t run_solve_d4(const LaunchDesc&, hipStream_t);
+hipError_t run_backward_d1(const LaunchDesc&, hipStream_t);
+hipError_t run_backward_d2(const LaunchDesc&, hipStream_t);
+hipError_t run_backward_d3(const LaunchDesc&, hipStream_t);
+hipError_t run_backward_d4(const LaunchDesc&, hipStream_t);
+
+size_t checkpoint_bytes(int64_t P, int S, int T, int D, int C) {
+  const int64_t nb = (P + S - 1) / S;
+  size_t mx = 0;
+  for (int rem = C; rem > 0;) {
+    const int g = next_group(rem);
+    size_t b = 0;
+    switch (D) {
+      case 1: b = ck_bytes_d<1>(nb, S, T, g); break;
+      case 2: b = ck_bytes_d<2>(nb, S, T, g); break;
+      case 3: b = ck_bytes_d<3>(nb, S, T, g); break;
+      case 4: b = ck_bytes_d<4>(nb, S, T, g); break;
+      default: return 0;
+    }
+    if (b > mx) mx = b;
+    rem -= g;
+  }
+  return mx;
+}
+
+hipError_t launch_solve(const LaunchDesc& L, hipStream_t stream) {
+  switch (L.D) {
+    case 1: return run_solve_d1(L, stream);
+    case 2: return run_solve_d2(L, stream);
+    case 3: return run_solve_d3(L, stream);
+    case 4: return run_solve_d4(L, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_backward(const LaunchDesc& L, hipStream_t stream) {
+  switch (L.D) {
+    case 1: return run_backward_d1(L, stream);
+    case 2: return run_backward_d2(L, stream);
+    case 3: return run_backward_d3(L, stream);
+    case 4: return run_backward_d4(L, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace whs

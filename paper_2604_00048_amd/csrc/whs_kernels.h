@@ -1,0 +1,31 @@
+// Internal launch interface between the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace whs {
+
+struct LaunchDesc {
+  int64_t P;
+  int T, D, C, S;
+  bool f64;        // storage type of x, z, g, lambda and grads
+  bool perdiff;    // lambda per difference row (else one scalar per series)
+  const uint8_t* w;
+  const void* lam;
+  const double* fac;  // whs_factor output, or the factor to write (whs_factor)
+  const void* rhs;    // x (solve) or g (backward)
+  const void* zin;    // z (backward)
+  void* out;          // z (solve) or grad_x (backward)
+  void* glam;         // grad_lambda (backward)
+  int32_t* info;
+  double* ws;         // checkpoint workspace
+};
+
+size_t checkpoint_bytes(int64_t P, int S, int T, int D, int C);
+hipError_t launch_solve(const LaunchDesc& L, hipStream_t stream);
+hipError_t launch_backward(const LaunchDesc& L, hipStream_t stream);
+hipError_t launch_factor(const LaunchDesc& L, hipStream_t stream);
+
+}  // namespace whs

@@ -261,3 +261,70 @@ def holdout_split(w: torch.Tensor, frac: float, gen) -> torch.Tensor:
     rank = torch.empty_like(order)
     rank.scatter_(1, order, torch.arange(T, device=w.device).expand(P, T).contiguous())
     return ((rank < k[:, None]) & (w != 0)).to(torch.uint8)
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads, generated chunk by chunk straight into the interleaved layout
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class Packed:
+    """A workload in the interleaved layout: ``x (nb,T,C,S)``, ``w (nb,T,S)``,
+    ``lam`` ``(P,)`` or ``(nb,T-d,S)``."""
+    x: torch.Tensor
+    w: torch.Tensor
+    lam: torch.Tensor
+    d: int
+    P: int
+    S: int
+
+    @property
+    def T(self):
+        return self.x.shape[1]
+
+    @property
+    def C(self):
+        return self.x.shape[2]
+
+    def series(self, idx) -> "Batch":
+        """Natural-layout copy (float64, on the CPU) of the series in ``idx``."""
+        idx = torch.as_tensor(idx, dtype=torch.long)
+        b, s = idx // self.S, idx % self.S
+        x = self.x[b.to(self.x.device), :, :, s.to(self.x.device)].to("cpu", torch.float64)
+        w = self.w[b.to(self.w.device), :, s.to(self.w.device)].to("cpu")
+        if self.lam.dim() == 1:
+            lam = self.lam[idx.to(self.lam.device)].to("cpu", torch.float64)
+        else:
+            lam = self.lam[b.to(self.lam.device), :, s.to(self.lam.device)].to("cpu", torch.float64)
+        return Batch(x, w, lam, self.d)
+
+
+def generate_packed(kind: str, P: int, S: int = 64, dtype=torch.float32, device="cpu", chunk: int = 8192,
+                    **kw) -> Packed:
+    """Generate ``kind`` in ``{"multiband", "heteroscedastic"}`` chunk by chunk.
+
+    Chunk ``i`` covers series ``[i*chunk, (i+1)*chunk)`` and is drawn from its
+    own generator, so the result depends on ``chunk`` (a multiple of ``S``).
+    """
+    assert chunk % S == 0
+    maker = {"multiband": multiband_homoscedastic, "heteroscedastic": heteroscedastic}[kind]
+    nb = n_blocks(P, S)
+    first = maker(min(chunk, P), device=device, chunk=0, **kw)
+    T, C, d = first.T, first.C, first.d
+    x = torch.zeros((nb, T, C, S), dtype=dtype, device=device)
+    w = torch.zeros((nb, T, S), dtype=torch.uint8, device=device)
+    per_diff = first.lam.dim() == 2
+    lam = torch.zeros((nb, T - d, S) if per_diff else (P,), dtype=dtype, device=device)
+    for i, p0 in enumerate(range(0, P, chunk)):
+        n = min(chunk, P - p0)
+        bt = first if i == 0 else maker(n, device=device, chunk=i, **kw)
+        b0, b1 = p0 // S, n_blocks(p0 + n, S)
+        x[b0:b1] = pack_series(bt.x.to(dtype), S)
+        w[b0:b1] = pack_rows(bt.w, S)
+        if per_diff:
+            lam[b0:b1] = pack_rows(bt.lam.to(dtype), S)
+        else:
+            lam[p0:p0 + n] = bt.lam.to(dtype)
+        del bt
+    return Packed(x, w, lam, d, P, S)

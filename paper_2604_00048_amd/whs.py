@@ -1,0 +1,249 @@
+"""Python binding of libwhs (ctypes).  Argument marshalling only.
+
+Every computation runs in the HIP kernels of ``libwhs.so``; this module
+checks tensor shapes, dtypes and devices, fills the descriptor, and passes
+device pointers and the current HIP stream.  It raises if the library is not
+built -- there is no CPU fallback.
+
+Layouts are the interleaved ones of the C header (``S`` series per block):
+
+* ``x``, ``z``, ``g``, ``grad_x``: ``(nb, T, C, S)``
+* ``w``: ``(nb, T, S)`` uint8
+* ``lam``, ``grad_lambda``: ``(P,)`` (one scalar per series) or
+  ``(nb, T-d, S)`` (one weight per difference row)
+* ``factor``: ``(nb, d+1, T, S)`` float64
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwhs.so")
+
+WHS_F32, WHS_F64 = 0, 1
+WHS_LAMBDA_SCALAR, WHS_LAMBDA_PER_DIFF = 0, 1
+
+
+class WhsDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_series", ctypes.c_int64),
+        ("T", ctypes.c_int32),
+        ("d", ctypes.c_int32),
+        ("n_rhs", ctypes.c_int32),
+        ("interleave", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("lambda_kind", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_SZ = ctypes.c_size_t
+_DP = ctypes.POINTER(WhsDesc)
+
+# symbol -> (restype, argtypes); the same names as include/whs.h
+SIGNATURES = {
+    "whs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "whs_version": (ctypes.c_int, []),
+    "whs_workspace_bytes": (_SZ, [_DP]),
+    "whs_factor_bytes": (_SZ, [_DP]),
+    "whs_factor": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP]),
+    "whs_solve": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "whs_backward": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libwhs.so`` (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "or `python -m paper_2604_00048_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_str(code: int) -> str:
+    return lib().whs_status_str(int(code)).decode()
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise RuntimeError(f"{what} failed: {status_str(code)} (status {code})")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return WHS_F32
+    if t.dtype == torch.float64:
+        return WHS_F64
+    raise TypeError(f"storage dtype must be float32 or float64, got {t.dtype}")
+
+
+def _need_gpu(*ts):
+    for t in ts:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError("libwhs works on device tensors only (got a CPU tensor)")
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous in the interleaved layout")
+
+
+def make_desc(P: int, T: int, d: int, C: int, S: int, dtype: int, lambda_kind: int) -> WhsDesc:
+    return WhsDesc(int(P), int(T), int(d), int(C), int(S), int(dtype), int(lambda_kind))
+
+
+def _lambda_kind(lam: torch.Tensor | None, P: int, nb: int, T: int, d: int, S: int) -> int:
+    if lam is None:
+        return WHS_LAMBDA_SCALAR
+    if lam.dim() == 1:
+        if lam.shape[0] != P:
+            raise ValueError(f"scalar weights need shape ({P},), got {tuple(lam.shape)}")
+        return WHS_LAMBDA_SCALAR
+    if tuple(lam.shape) != (nb, T - d, S):
+        raise ValueError(f"per-difference weights need shape {(nb, T - d, S)}, got {tuple(lam.shape)}")
+    return WHS_LAMBDA_PER_DIFF
+
+
+def workspace_bytes(desc: WhsDesc) -> int:
+    return int(lib().whs_workspace_bytes(ctypes.byref(desc)))
+
+
+def _workspace(desc: WhsDesc, device, workspace):
+    n = workspace_bytes(desc)
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < n:
+            raise ValueError(f"workspace has {workspace.numel() * workspace.element_size()} bytes, needs {n}")
+        return workspace, n
+    return torch.empty(max(n, 8), dtype=torch.uint8, device=device), n
+
+
+def _geometry(x: torch.Tensor, P: int | None):
+    if x.dim() != 4:
+        raise ValueError(f"series need the interleaved shape (nb, T, C, S), got {tuple(x.shape)}")
+    nb, T, C, S = x.shape
+    if P is None:
+        P = nb * S
+    if not (nb - 1) * S < P <= nb * S and not (P == 0 and nb == 0):
+        raise ValueError(f"P={P} does not fit {nb} blocks of {S}")
+    return int(nb), int(T), int(C), int(S), int(P)
+
+
+def whs_factor(w: torch.Tensor, lam: torch.Tensor, d: int, P: int | None = None, factor=None, info=None):
+    """Cholesky factor of Omega in lower band storage (Alg. 1 output, Fig. 2 layout).
+
+    Returns ``(factor (nb, d+1, T, S) float64, info (P,) int32)``.
+    """
+    _need_gpu(w, lam, factor, info)
+    nb, T, S = w.shape
+    P = nb * S if P is None else int(P)
+    kind = _lambda_kind(lam, P, nb, T, d, S)
+    desc = make_desc(P, T, d, 1, S, _dtype_code(lam), kind)
+    if factor is None:
+        factor = torch.empty((nb, d + 1, T, S), dtype=torch.float64, device=w.device)
+    if info is None:
+        info = torch.empty(P, dtype=torch.int32, device=w.device)
+    _check(lib().whs_factor(ctypes.byref(desc), _ptr(w), _ptr(lam), _ptr(factor), _ptr(info), _stream(w.device)),
+           "whs_factor")
+    return factor, info
+
+
+def whs_solve(x: torch.Tensor, w: torch.Tensor, lam: torch.Tensor | None, d: int, P: int | None = None,
+              factor=None, z=None, info=None, workspace=None):
+    """``z = Omega^{-1} W x`` per series and band.  Returns ``(z, info)``."""
+    _need_gpu(x, w, lam, factor, z, info, workspace)
+    nb, T, C, S, P = _geometry(x, P)
+    if tuple(w.shape) != (nb, T, S) or w.dtype != torch.uint8:
+        raise ValueError(f"w must be uint8 of shape {(nb, T, S)}")
+    if lam is not None and lam.dtype != x.dtype:
+        raise TypeError("lambda must have the storage dtype of x")
+    kind = _lambda_kind(lam, P, nb, T, d, S)
+    desc = make_desc(P, T, d, C, S, _dtype_code(x), kind)
+    if z is None:
+        z = torch.empty_like(x)
+    if info is None:
+        info = torch.empty(P, dtype=torch.int32, device=x.device)
+    ws, n = _workspace(desc, x.device, workspace)
+    _check(lib().whs_solve(ctypes.byref(desc), _ptr(w), _ptr(lam), _ptr(factor), _ptr(x), _ptr(z), _ptr(info),
+                           _ptr(ws), ws.numel() * ws.element_size(), _stream(x.device)), "whs_solve")
+    return z, info
+
+
+def whs_backward(w: torch.Tensor, lam: torch.Tensor | None, z: torch.Tensor, g: torch.Tensor, d: int,
+                 P: int | None = None, factor=None, need_x: bool = True, need_lambda: bool = True,
+                 grad_x=None, grad_lambda=None, info=None, workspace=None, lambda_kind: int | None = None):
+    """Adjoint against ``g``: ``grad_x = W Omega^{-1} g``, ``grad_lambda_k = -(D u)_k (D z)_k``.
+
+    Returns ``(grad_x or None, grad_lambda or None, info)``.
+    """
+    _need_gpu(w, lam, z, g, factor, grad_x, grad_lambda, info, workspace)
+    nb, T, C, S, P = _geometry(z, P)
+    if tuple(g.shape) != tuple(z.shape) or g.dtype != z.dtype:
+        raise ValueError("g must match z in shape and dtype")
+    kind = _lambda_kind(lam, P, nb, T, d, S) if lambda_kind is None else int(lambda_kind)
+    desc = make_desc(P, T, d, C, S, _dtype_code(z), kind)
+    if need_x and grad_x is None:
+        grad_x = torch.empty_like(g)
+    if need_lambda and grad_lambda is None:
+        shape = (P,) if kind == WHS_LAMBDA_SCALAR else (nb, T - d, S)
+        grad_lambda = torch.empty(shape, dtype=z.dtype, device=z.device)
+    if info is None:
+        info = torch.empty(P, dtype=torch.int32, device=z.device)
+    ws, n = _workspace(desc, z.device, workspace)
+    _check(lib().whs_backward(ctypes.byref(desc), _ptr(w), _ptr(lam), _ptr(factor), _ptr(z), _ptr(g),
+                              _ptr(grad_x if need_x else None), _ptr(grad_lambda if need_lambda else None),
+                              _ptr(info), _ptr(ws), ws.numel() * ws.element_size(), _stream(z.device)),
+           "whs_backward")
+    return (grad_x if need_x else None), (grad_lambda if need_lambda else None), info
+
+
+class WhittakerFn(torch.autograd.Function):
+    """``z = (W + D^T Lambda D)^{-1} W x`` as a differentiable layer (Sec. II-C).
+
+    ``apply(x, lam, w, d, P)`` on interleaved tensors; gradients flow to ``x``
+    and ``lam`` through the adjoint kernel (one extra banded solve).
+    """
+
+    @staticmethod
+    def forward(ctx, x, lam, w, d, P=None):
+        z, info = whs_solve(x, w, lam, d, P)
+        ctx.save_for_backward(w, lam, z)
+        ctx.d = d
+        ctx.P = P
+        ctx.mark_non_differentiable(info)
+        return z, info
+
+    @staticmethod
+    def backward(ctx, gz, ginfo):
+        w, lam, z = ctx.saved_tensors
+        need_x, need_l = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        if not (need_x or need_l):
+            return None, None, None, None, None
+        gx, gl, _ = whs_backward(w, lam, z, gz.contiguous(), ctx.d, ctx.P, need_x=need_x, need_lambda=need_l)
+        return gx, gl, None, None, None
+
+
+def smooth(x, lam, w, d, P=None):
+    """Differentiable smoother; returns ``z`` only."""
+    z, _ = WhittakerFn.apply(x, lam, w, d, P)
+    return z

@@ -1,0 +1,78 @@
+"""Seeded cases shared by the GPU parity tests: inputs from the generator
+module, expected values from the CPU oracle only."""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from oracle import whs_ref as R
+from paper_2604_00048_amd import synth
+
+
+def random_case(P, T, d, C=1, per_diff=True, seed=0, p_obs=0.3, lam_lo=0.0, lam_hi=4.0, dtype=torch.float64):
+    """Natural-layout float64 numpy inputs, rounded through ``dtype`` (what the GPU sees)."""
+    r = np.random.default_rng(seed)
+    x = r.normal(size=(P, T, C)) * 0.1 + 0.3
+    w = (r.random((P, T)) < p_obs).astype(np.uint8)
+    w[:, ::max(T // (d + 2), 1)] = 1  # at least d+1 observations in every series
+    if per_diff:
+        lam = 10.0 ** r.uniform(lam_lo, lam_hi, size=(P, T - d))
+    else:
+        lam = 10.0 ** r.uniform(lam_lo, lam_hi, size=P)
+    x = np.where(w[:, :, None] != 0, x, 0.0)
+    x = torch.tensor(x).to(dtype).double().numpy()
+    lam = torch.tensor(lam).to(dtype).double().numpy()
+    return x, w, lam
+
+
+def to_device(x, w, lam, S, dtype, device="cuda"):
+    xt = synth.pack_series(torch.tensor(x, dtype=dtype), S).to(device)
+    wt = synth.pack_rows(torch.tensor(w), S).to(device)
+    lam = np.asarray(lam)
+    if lam.ndim == 1:
+        lt = torch.tensor(lam, dtype=dtype).to(device)
+    else:
+        lt = synth.pack_rows(torch.tensor(lam, dtype=dtype), S).to(device)
+    return xt, wt, lt
+
+
+def from_device_series(zt, P):
+    return synth.unpack_series(zt.cpu(), P).double().numpy()
+
+
+def from_device_rows(lt, P):
+    if lt.dim() == 1:
+        return lt.cpu().double().numpy()[:P]
+    return synth.unpack_rows(lt.cpu(), P).double().numpy()
+
+
+def lapack_spread(x, w, lam, d, zref):
+    """Norm-wise distance between the oracle and LAPACK's banded solver per series
+    (how far two correct FP64 solvers already differ on this input)."""
+    import scipy.linalg
+    AB = R.omega_band(w, lam, d)
+    out = np.zeros(x.shape[0])
+    for p in range(x.shape[0]):
+        ref = scipy.linalg.solveh_banded(AB[p], np.where(w[p][:, None] != 0, x[p], 0.0), lower=True)
+        out[p] = np.abs(ref - zref[p]).max() / max(np.abs(ref).max(), 1e-300)
+    return out
+
+
+def assert_solution(z, zref, x, w, lam, d, f64: bool, info=None):
+    """FP64: per-series error <= max(1e-10, 10 x LAPACK spread); FP32 storage:
+    <= 1e-4.  Always: componentwise backward error <= 1e-13 (FP64) / 1e-6 (FP32)."""
+    ok = np.ones(z.shape[0], bool) if info is None else (info == 0)
+    err = R.rel_err(z[ok], zref[ok])
+    if f64:
+        bad = err > 1e-10
+        if bad.any():
+            spread = lapack_spread(x[ok][bad], w[ok][bad], np.asarray(lam)[ok][bad], d, zref[ok][bad])
+            assert (err[bad] <= 10 * spread).all(), (err[bad].max(), spread.max())
+        be = R.backward_error(x[ok], w[ok], np.asarray(lam)[ok], d, z[ok])
+        assert be.max() <= 1e-13, be.max()
+    else:
+        assert err.max() <= 1e-4, err.max()
+        be = R.backward_error(x[ok], w[ok], np.asarray(lam)[ok], d, z[ok])
+        assert be.max() <= 1e-6, be.max()
+    return err

@@ -1,0 +1,113 @@
+"""The C-ABI library loads and exports every declared symbol; host-side
+argument checks reject bad calls before anything is launched (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2604_00048_amd import whs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    src = open(os.path.join(ROOT, "include", header)).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(whs_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_built():
+    assert os.path.exists(whs.LIB_PATH), "run __graft_entry__.build() first"
+
+
+def test_every_declared_symbol_is_exported():
+    L = whs.lib()
+    names = _declared("whs.h")
+    assert {"whs_solve", "whs_backward", "whs_factor", "whs_status_str"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in whs.SIGNATURES, f"binding lacks {n}"
+
+
+def test_status_strings_and_version():
+    assert whs.lib().whs_version() >= 100
+    for code in (0, -1, -2, -3, -4):
+        assert whs.status_str(code) != "unknown status"
+    assert whs.status_str(-99) == "unknown status"
+
+
+def _solve_raw(desc, w=None, lam=None, x=None, z=None, ws=None, nws=0):
+    L = whs.lib()
+    return L.whs_solve(ctypes.byref(desc), w, lam, None, x, z, None, ws, nws, None)
+
+
+FAKE = ctypes.c_void_p(1 << 20)          # never dereferenced: checks fail first
+FAKE_ODD = ctypes.c_void_p((1 << 20) + 2)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(T=2, d=2),          # T <= d
+    dict(d=0),
+    dict(n_rhs=0),
+    dict(interleave=0),
+    dict(dtype=7),
+    dict(lambda_kind=3),
+    dict(n_series=-1),
+])
+def test_descriptor_validation(bad):
+    kw = dict(n_series=10, T=50, d=2, n_rhs=1, interleave=64, dtype=0, lambda_kind=0)
+    kw.update(bad)
+    desc = whs.make_desc(kw["n_series"], kw["T"], kw["d"], kw["n_rhs"], kw["interleave"], kw["dtype"],
+                         kw["lambda_kind"])
+    assert _solve_raw(desc, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 30) == -1
+
+
+def test_order_above_four_is_unsupported():
+    desc = whs.make_desc(10, 50, 5, 1, 64, 0, 0)
+    assert _solve_raw(desc, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 30) == -2
+
+
+def test_null_and_misaligned_pointers():
+    desc = whs.make_desc(10, 50, 2, 1, 64, 0, 0)
+    assert _solve_raw(desc, None, FAKE, FAKE, FAKE, FAKE, 1 << 30) == -1
+    assert _solve_raw(desc, FAKE, None, FAKE, FAKE, FAKE, 1 << 30) == -1   # no lambda and no factor
+    assert _solve_raw(desc, FAKE, FAKE, FAKE_ODD, FAKE, FAKE, 1 << 30) == -1
+    assert _solve_raw(desc, FAKE, FAKE, FAKE, FAKE, None, 0) == -4          # workspace missing
+    need = whs.workspace_bytes(desc)
+    assert _solve_raw(desc, FAKE, FAKE, FAKE, FAKE, FAKE, need - 8) == -4
+
+
+def test_empty_batch_is_a_noop():
+    desc = whs.make_desc(0, 50, 2, 1, 64, 0, 0)
+    assert whs.workspace_bytes(desc) == 0
+    assert _solve_raw(desc) == 0
+    L = whs.lib()
+    assert L.whs_backward(ctypes.byref(desc), None, None, None, None, None, None, None, None, None, 0, None) == 0
+    assert L.whs_factor(ctypes.byref(desc), None, None, None, None, None) == 0
+
+
+def test_workspace_and_factor_sizes():
+    # order 2, one band: 2 + 1 + 2 = 5 doubles per tile of 16 steps per series
+    desc = whs.make_desc(100, 365, 2, 1, 64, 0, 1)
+    tiles = (365 + 15) // 16
+    assert whs.workspace_bytes(desc) == 2 * tiles * 5 * 64 * 8
+    assert whs.lib().whs_factor_bytes(ctypes.byref(desc)) == 128 * 3 * 365 * 8
+
+
+def test_backward_validation():
+    L = whs.lib()
+    desc = whs.make_desc(10, 50, 2, 1, 64, 1, 1)
+    ws = 1 << 30
+    assert L.whs_backward(ctypes.byref(desc), FAKE, FAKE, None, None, FAKE, FAKE, FAKE, None, FAKE, ws, None) == -1
+    assert L.whs_backward(ctypes.byref(desc), FAKE, FAKE, None, FAKE, FAKE, FAKE_ODD, None, None, FAKE, ws,
+                          None) == -1
+
+
+def test_binding_refuses_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    x = torch.zeros((1, 10, 1, 64))
+    w = torch.zeros((1, 10, 64), dtype=torch.uint8)
+    with pytest.raises(ValueError):
+        whs.whs_solve(x, w, torch.ones(64), 2)
