@@ -19,6 +19,7 @@
 // registers.
 #include <hip/hip_runtime.h>
 
+#include "whs_fast.h"
 #include "whs_kernels.h"
 #include "whs_step.h"
 
@@ -416,12 +417,38 @@ __global__ __launch_bounds__(256) void k_two_sweep(Args a) {
 
 template <int D, int C>
 constexpr int tile_depth() {
-  return C <= 2 ? 16 : 8;
+  return C == 1 ? 24 : (C == 2 ? 16 : 8);
 }
 
 template <int D, int C, typename TS, Src SRC, Mode MODE, bool PERDIFF>
 hipError_t launch_two_sweep(const LaunchDesc& L, int c0, int write_info, hipStream_t stream) {
   constexpr int B = tile_depth<D, C>();
+  if constexpr (SRC == Src::Fused) {
+    if (L.S % 64 == 0 && L.P < ((int64_t)1 << 31)) {
+      FastArgs f;
+      f.P = L.P;
+      f.T = L.T;
+      f.S = L.S;
+      f.Ctot = L.C;
+      f.c0 = c0;
+      f.nt = (L.T + B - 1) / B;
+      f.w = L.w;
+      f.lam = L.lam;
+      f.rhs = L.rhs;
+      f.zin = L.zin;
+      f.out = L.out;
+      f.glam = L.glam;
+      f.info = L.info;
+      f.ck = L.ws;
+      f.write_info = write_info;
+      f.glam_accum = c0 > 0;
+      const int threads = 256;
+      const int64_t blocks = (L.P + threads - 1) / threads;
+      hipLaunchKernelGGL((k_fast<D, C, B, TS, MODE == Mode::Backward, PERDIFF>), dim3((unsigned)blocks),
+                         dim3(threads), 0, stream, f);
+      return hipGetLastError();
+    }
+  }
   Args a;
   a.P = L.P;
   a.T = L.T;

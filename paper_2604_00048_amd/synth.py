@@ -111,8 +111,11 @@ def gp_log10_field(P: int, n: int, gen, device, mean=2.0, sd=0.5, ell=60.0,
     tk = torch.arange(-half, half + 1, dtype=torch.float64, device=device)
     ker = torch.exp(-0.5 * (tk / ks) ** 2)
     ker = ker / torch.sqrt((ker ** 2).sum())  # unit-variance output
-    wn = torch.randn((P, 1, n + 2 * half), generator=gen, device=device, dtype=torch.float64)
-    f = torch.nn.functional.conv1d(wn, ker.view(1, 1, -1)).view(P, n)
+    wn = torch.randn((P, n + 2 * half), generator=gen, device=device, dtype=torch.float64)
+    # valid cross-correlation f[i] = sum_j ker[j] wn[i + j], by one batched FFT
+    L = 1 << int(math.ceil(math.log2(n + 4 * half + 1)))
+    spec = torch.fft.rfft(wn, L) * torch.conj(torch.fft.rfft(ker, L))
+    f = torch.fft.irfft(spec, L)[:, :n]
     f = mean + sd * f
     hit = torch.rand((P, n), generator=gen, device=device, dtype=torch.float64) < drop_p
     return f - drop * hit.to(torch.float64)

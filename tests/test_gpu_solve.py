@@ -183,5 +183,8 @@ def test_autograd_function_matches_oracle():
     (z * g).sum().backward()
     gn = from_device_series(g, P)
     gx_ref, gl_ref, _ = R.vjp(x, w, lam, d, gn)
-    np.testing.assert_allclose(from_device_series(xt.grad, P), gx_ref, rtol=1e-8, atol=1e-11)
-    np.testing.assert_allclose(from_device_rows(lt.grad, P), gl_ref, rtol=1e-7, atol=1e-11)
+    # norm-wise per series: single entries of -(D u)(D z) cancel to ~1e-12 of the series scale
+    gx = from_device_series(xt.grad, P)
+    gl = from_device_rows(lt.grad, P)
+    assert (np.abs(gx - gx_ref).max(axis=(1, 2)) / np.abs(gx_ref).max(axis=(1, 2))).max() < 1e-9
+    assert (np.abs(gl - gl_ref).max(axis=1) / np.abs(gl_ref).max(axis=1)).max() < 1e-9
