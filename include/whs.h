@@ -128,6 +128,83 @@ int whs_backward(const whs_desc* desc, const uint8_t* w, const void* lambda,
                  void* grad_x, void* grad_lambda, int32_t* info,
                  void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * whs_gcv -- one scalar weight per series chosen by generalised
+ * cross-validation over a grid (the plain form's per-pixel selection; the
+ * paper's introduction cites per-pixel cross-validated grid search as the
+ * classical way to tune the weight).  For each grid value lambda_g the
+ * series is smoothed (eq. (2)) and scored
+ *     GCV_g = m RSS / (m - ED)^2,  m = sum_t w_t,
+ *     RSS = sum_t w_t (x_t - z_t)^2,  ED = sum_t w_t (Omega^{-1})_{tt},
+ * with diag(Omega^{-1}) from the selected-inverse recurrence on the banded
+ * factor.  lambda_best[p] is the grid value of the first minimum (NaN if
+ * every grid value failed).  Requires n_rhs == 1, lambda_kind == SCALAR
+ * (it describes lambda_best), interleave a multiple of 64
+ * (WHS_ERR_UNSUPPORTED otherwise).  grid: device FP64[n_grid], n_grid >= 1.
+ * scores: device FP64[P][n_grid] or NULL.  info: 0 if some grid value
+ * succeeded, else the first grid value's failure code.  x is read at w = 1
+ * only.  The workspace size is whs_gcv_workspace_bytes(desc).
+ */
+size_t whs_gcv_workspace_bytes(const whs_desc* desc);
+int whs_gcv(const whs_desc* desc, const uint8_t* w, const void* x, const double* grid, int32_t n_grid,
+            void* lambda_best, double* scores, int32_t* info, void* workspace, size_t workspace_bytes,
+            void* stream);
+
+/*
+ * Uneven batches in one persistent launch.
+ *
+ * A group is a set of series sharing a length T and an order d, stored in
+ * the interleaved layouts above with interleave 64 inside one shared buffer
+ * per array: the group's first block starts at element x_off of x and z,
+ * w_off of w, lam_off of lambda (SCALAR: the group's first series; PER_DIFF:
+ * its first block of T-d rows) and info_off of info.  Padding every series
+ * to one common T with w = 0 would give the same values on the original
+ * samples (unobserved samples are padding, Sec. II) but would read and
+ * solve the padding; groups avoid that.
+ *
+ * whs_plan_create copies the group table and a longest-first list of
+ * 64-series work items to the device and allocates the plan's checkpoint
+ * space (the only device memory the library allocates).  Requires
+ * n_rhs == 1 and interleave == 64 (WHS_ERR_UNSUPPORTED otherwise).
+ * whs_plan_solve runs every group in one persistent kernel whose
+ * wavefronts take items from a device queue.  whs_plan_graph_launch does the
+ * same through a HIP graph owned by the plan (built on first use, its
+ * arguments updated on later calls).  whs_plan_autotune times the candidate
+ * configurations (tile-depth profile 0/1/2: 8/16/24 steps for order 1, less
+ * for higher orders; 1/2/4 wavefronts per workgroup; 1/2 resident
+ * wavefronts per SIMD) on the given buffers (z is overwritten) and
+ * keeps the fastest; results are cached in the text file named by
+ * $WHS_TUNE_CACHE (default $HOME/.cache/whs_tune.txt), keyed by the device
+ * and the (T, d, blocks) of every group; force = 1 ignores the cache.  The
+ * configuration changes timing only: every choice gives bitwise-identical z.
+ * A plan is used by one stream at a time.
+ */
+typedef struct {
+  int64_t n_series;  /* series in the group (>= 0)                   */
+  int32_t T;         /* their common length, T > d                   */
+  int32_t d;         /* their common order, 1..4                     */
+  int64_t x_off;     /* element offsets of the group in each buffer  */
+  int64_t w_off;
+  int64_t lam_off;
+  int64_t info_off;
+} whs_group;
+
+typedef struct whs_plan whs_plan;
+
+int whs_plan_create(whs_plan** plan, const whs_group* groups, int32_t n_groups, int32_t n_rhs, int32_t dtype,
+                    int32_t lambda_kind, int32_t interleave);
+int whs_plan_solve(whs_plan* plan, const uint8_t* w, const void* lambda, const void* x, void* z, int32_t* info,
+                   void* stream);
+int whs_plan_graph_launch(whs_plan* plan, const uint8_t* w, const void* lambda, const void* x, void* z,
+                          int32_t* info, void* stream);
+int whs_plan_autotune(whs_plan* plan, const uint8_t* w, const void* lambda, const void* x, void* z, int32_t force,
+                      void* stream);
+/* Current configuration (tile profile, wavefronts per workgroup, per SIMD)
+ * and number of work items; any pointer may be NULL. */
+int whs_plan_config(const whs_plan* plan, int32_t* tile, int32_t* waves_per_block, int32_t* waves_per_simd,
+                    int32_t* n_items);
+void whs_plan_destroy(whs_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -131,4 +131,41 @@ int whs_backward(const whs_desc* desc, const uint8_t* w, const void* lambda, con
   return hip_status(whs::launch_backward(L, static_cast<hipStream_t>(stream)));
 }
 
+size_t whs_gcv_workspace_bytes(const whs_desc* desc) {
+  if (check_desc(desc) != WHS_OK || desc->n_series == 0) return 0;
+  return whs::gcv_checkpoint_bytes(desc->n_series, desc->interleave, desc->T, desc->d);
+}
+
+int whs_gcv(const whs_desc* desc, const uint8_t* w, const void* x, const double* grid, int32_t n_grid,
+            void* lambda_best, double* scores, int32_t* info, void* workspace, size_t workspace_bytes,
+            void* stream) {
+  int st = check_desc(desc);
+  if (st != WHS_OK) return st;
+  if (desc->n_rhs != 1 || desc->lambda_kind != WHS_LAMBDA_SCALAR) return WHS_ERR_UNSUPPORTED;
+  if (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31)) return WHS_ERR_UNSUPPORTED;
+  if (n_grid < 1) return WHS_ERR_ARG;
+  if (desc->n_series == 0) return WHS_OK;
+  if (!w || !x || !grid || !lambda_best) return WHS_ERR_ARG;
+  const size_t e = elem(desc);
+  if (!aligned(x, e) || !aligned(lambda_best, e) || !aligned(grid, 8) || !aligned(scores, 8) || !aligned(info, 4))
+    return WHS_ERR_ARG;
+  if (!workspace || workspace_bytes < whs_gcv_workspace_bytes(desc) || !aligned(workspace, 8))
+    return WHS_ERR_WORKSPACE;
+  whs::GcvLaunch L{};
+  L.P = desc->n_series;
+  L.T = desc->T;
+  L.D = desc->d;
+  L.S = desc->interleave;
+  L.n_grid = n_grid;
+  L.f64 = desc->dtype == WHS_F64;
+  L.w = w;
+  L.x = x;
+  L.grid = grid;
+  L.lam_best = lambda_best;
+  L.scores = scores;
+  L.info = info;
+  L.ws = static_cast<double*>(workspace);
+  return hip_status(whs::launch_gcv(L, static_cast<hipStream_t>(stream)));
+}
+
 }  // extern "C"

@@ -15,20 +15,24 @@ hipError_t run_backward_d3(const LaunchDesc&, hipStream_t);
 hipError_t run_backward_d4(const LaunchDesc&, hipStream_t);
 
 size_t checkpoint_bytes(int64_t P, int S, int T, int D, int C) {
+  // the largest checkpoint area any call with this descriptor can use:
+  // the fast grouping and the generic one (given factor) are both covered
   const int64_t nb = (P + S - 1) / S;
   size_t mx = 0;
-  for (int rem = C; rem > 0;) {
-    const int g = next_group(rem);
-    size_t b = 0;
-    switch (D) {
-      case 1: b = ck_bytes_d<1>(nb, S, T, g); break;
-      case 2: b = ck_bytes_d<2>(nb, S, T, g); break;
-      case 3: b = ck_bytes_d<3>(nb, S, T, g); break;
-      case 4: b = ck_bytes_d<4>(nb, S, T, g); break;
-      default: return 0;
+  for (int fast = 0; fast < 2; ++fast) {
+    for (int rem = C; rem > 0;) {
+      const int g = next_group(rem, fast != 0);
+      size_t b = 0;
+      switch (D) {
+        case 1: b = ck_bytes_d<1>(nb, S, T, g); break;
+        case 2: b = ck_bytes_d<2>(nb, S, T, g); break;
+        case 3: b = ck_bytes_d<3>(nb, S, T, g); break;
+        case 4: b = ck_bytes_d<4>(nb, S, T, g); break;
+        default: return 0;
+      }
+      if (b > mx) mx = b;
+      rem -= g;
     }
-    if (b > mx) mx = b;
-    rem -= g;
   }
   return mx;
 }

@@ -29,3 +29,23 @@ hipError_t launch_backward(const LaunchDesc& L, hipStream_t stream);
 hipError_t launch_factor(const LaunchDesc& L, hipStream_t stream);
 
 }  // namespace whs
+
+namespace whs {
+
+struct GcvLaunch {
+  int64_t P;
+  int T, D, S, n_grid;
+  bool f64;
+  const uint8_t* w;
+  const void* x;
+  const double* grid;
+  void* lam_best;
+  double* scores;
+  int32_t* info;
+  double* ws;
+};
+
+size_t gcv_checkpoint_bytes(int64_t P, int S, int T, int D);
+hipError_t launch_gcv(const GcvLaunch& L, hipStream_t stream);
+
+}  // namespace whs

@@ -421,34 +421,35 @@ constexpr int tile_depth() {
 }
 
 template <int D, int C, typename TS, Src SRC, Mode MODE, bool PERDIFF>
-hipError_t launch_two_sweep(const LaunchDesc& L, int c0, int write_info, hipStream_t stream) {
+hipError_t launch_fast(const LaunchDesc& L, int c0, int write_info, hipStream_t stream) {
   constexpr int B = tile_depth<D, C>();
-  if constexpr (SRC == Src::Fused) {
-    if (L.S % 64 == 0 && L.P < ((int64_t)1 << 31)) {
-      FastArgs f;
-      f.P = L.P;
-      f.T = L.T;
-      f.S = L.S;
-      f.Ctot = L.C;
-      f.c0 = c0;
-      f.nt = (L.T + B - 1) / B;
-      f.w = L.w;
-      f.lam = L.lam;
-      f.rhs = L.rhs;
-      f.zin = L.zin;
-      f.out = L.out;
-      f.glam = L.glam;
-      f.info = L.info;
-      f.ck = L.ws;
-      f.write_info = write_info;
-      f.glam_accum = c0 > 0;
-      const int threads = 256;
-      const int64_t blocks = (L.P + threads - 1) / threads;
-      hipLaunchKernelGGL((k_fast<D, C, B, TS, MODE == Mode::Backward, PERDIFF>), dim3((unsigned)blocks),
-                         dim3(threads), 0, stream, f);
-      return hipGetLastError();
-    }
-  }
+  FastArgs f;
+  f.P = L.P;
+  f.T = L.T;
+  f.S = L.S;
+  f.Ctot = L.C;
+  f.c0 = c0;
+  f.nt = (L.T + B - 1) / B;
+  f.w = L.w;
+  f.lam = L.lam;
+  f.rhs = L.rhs;
+  f.zin = L.zin;
+  f.out = L.out;
+  f.glam = L.glam;
+  f.info = L.info;
+  f.ck = L.ws;
+  f.write_info = write_info;
+  f.glam_accum = c0 > 0;
+  const int threads = 256;
+  const int64_t blocks = (L.P + threads - 1) / threads;
+  hipLaunchKernelGGL((k_fast<D, C, B, TS, MODE == Mode::Backward, PERDIFF>), dim3((unsigned)blocks), dim3(threads),
+                     0, stream, f);
+  return hipGetLastError();
+}
+
+template <int D, int C, typename TS, Src SRC, Mode MODE, bool PERDIFF>
+hipError_t launch_generic(const LaunchDesc& L, int c0, int write_info, hipStream_t stream) {
+  constexpr int B = tile_depth<D, C>();
   Args a;
   a.P = L.P;
   a.T = L.T;
@@ -481,13 +482,18 @@ size_t ck_bytes_for(int64_t nb, int S, int T) {
   return (size_t)nb * nt * ck_fields<D, C>() * S * sizeof(double);
 }
 
-// RHS group sizes instantiated; a launch covers C by groups of these sizes.
-constexpr int kGroups[] = {10, 4, 2, 1};
+// RHS group sizes: the fast path (interleave a multiple of 64, weights and
+// mask given) is built for 10, 4, 2 and 1 bands per launch; the generic path
+// (any interleave, or a given factor) for 2 and 1.  A call covers C bands by
+// greedy groups; every group recomputes the same factor.
+inline bool fast_path(const LaunchDesc& L) { return !L.fac && L.S % 64 == 0 && L.P < ((int64_t)1 << 31); }
 
-inline int next_group(int remaining) {
-  for (int g : kGroups)
-    if (g <= remaining) return g;
-  return 1;
+inline int next_group(int remaining, bool fast) {
+  if (fast) {
+    for (int g : {10, 4, 2, 1})
+      if (g <= remaining) return g;
+  }
+  return remaining >= 2 ? 2 : 1;
 }
 
 template <int D>
@@ -502,19 +508,27 @@ inline size_t ck_bytes_d(int64_t nb, int S, int T, int g) {
 
 template <int D, typename TS, Src SRC, Mode MODE, bool PERDIFF>
 hipError_t run_groups(const LaunchDesc& L, hipStream_t stream) {
+  const bool fast = SRC == Src::Fused && fast_path(L);
   int c0 = 0;
   while (c0 < L.C) {
-    const int g = next_group(L.C - c0);
+    const int g = next_group(L.C - c0, fast);
+    const int wi = c0 == 0;  // the first group writes info; later groups add to grad_lambda
     hipError_t e;
-    const int wi = c0 == 0;
-    // every group recomputes the same factor; the first one writes info,
-    // the backward groups each contribute to grad_lambda via accumulation
-    switch (g) {
-      case 10: e = launch_two_sweep<D, 10, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
-      case 4: e = launch_two_sweep<D, 4, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
-      case 2: e = launch_two_sweep<D, 2, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
-      default: e = launch_two_sweep<D, 1, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
+    if constexpr (SRC == Src::Fused) {
+      if (fast) {
+        switch (g) {
+          case 10: e = launch_fast<D, 10, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
+          case 4: e = launch_fast<D, 4, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
+          case 2: e = launch_fast<D, 2, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
+          default: e = launch_fast<D, 1, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
+        }
+        if (e != hipSuccess) return e;
+        c0 += g;
+        continue;
+      }
     }
+    e = g == 2 ? launch_generic<D, 2, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream)
+               : launch_generic<D, 1, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream);
     if (e != hipSuccess) return e;
     c0 += g;
   }

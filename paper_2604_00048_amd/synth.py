@@ -331,3 +331,39 @@ def generate_packed(kind: str, P: int, S: int = 64, dtype=torch.float32, device=
             lam[p0:p0 + n] = bt.lam.to(dtype)
         del bt
     return Packed(x, w, lam, d, P, S)
+
+
+def pack_groups(groups, S: int = 64, dtype=torch.float32, device="cpu"):
+    """Pack ``[((T, d), Batch), ...]`` into flat interleaved buffers.
+
+    Returns ``(x, w, lam, descs)``: 1-D tensors holding every group's
+    interleaved blocks back to back, and one descriptor dict per group with
+    the element offsets ``x_off, w_off, lam_off, info_off`` (scalar weights:
+    one per series, concatenated).
+    """
+    xs, ws, ls, descs = [], [], [], []
+    xo = wo = lo = io = 0
+    for (T, d), b in groups:
+        xi = pack_series(b.x.to(dtype), S).reshape(-1)
+        wi = pack_rows(b.w, S).reshape(-1)
+        if b.lam.dim() == 2:
+            li = pack_rows(b.lam.to(dtype), S).reshape(-1)
+        else:
+            li = b.lam.to(dtype).reshape(-1)
+        descs.append({"n_series": b.P, "T": T, "d": d, "x_off": xo, "w_off": wo, "lam_off": lo, "info_off": io})
+        xs.append(xi)
+        ws.append(wi)
+        ls.append(li)
+        xo += xi.numel()
+        wo += wi.numel()
+        lo += li.numel()
+        io += b.P
+    return (torch.cat(xs).to(device), torch.cat(ws).to(device), torch.cat(ls).to(device), descs)
+
+
+def unpack_group(buf: torch.Tensor, desc: dict, C: int = 1, S: int = 64) -> torch.Tensor:
+    """Natural-layout ``(n, T, C)`` view of one group inside a flat buffer from ``pack_groups``."""
+    n, T = desc["n_series"], desc["T"]
+    nb = n_blocks(n, S)
+    blk = buf[desc["x_off"]:desc["x_off"] + nb * T * C * S].view(nb, T, C, S)
+    return unpack_series(blk, n)

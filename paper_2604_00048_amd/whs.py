@@ -40,6 +40,18 @@ class WhsDesc(ctypes.Structure):
     ]
 
 
+class WhsGroup(ctypes.Structure):
+    _fields_ = [
+        ("n_series", ctypes.c_int64),
+        ("T", ctypes.c_int32),
+        ("d", ctypes.c_int32),
+        ("x_off", ctypes.c_int64),
+        ("w_off", ctypes.c_int64),
+        ("lam_off", ctypes.c_int64),
+        ("info_off", ctypes.c_int64),
+    ]
+
+
 _lib = None
 
 _VP = ctypes.c_void_p
@@ -55,6 +67,16 @@ SIGNATURES = {
     "whs_factor": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP]),
     "whs_solve": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "whs_backward": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "whs_gcv_workspace_bytes": (_SZ, [_DP]),
+    "whs_gcv": (ctypes.c_int, [_DP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "whs_plan_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(WhsGroup), ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "whs_plan_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "whs_plan_graph_launch": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "whs_plan_autotune": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
+    "whs_plan_config": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "whs_plan_destroy": (None, [_VP]),
 }
 
 
@@ -215,6 +237,91 @@ def whs_backward(w: torch.Tensor, lam: torch.Tensor | None, z: torch.Tensor, g: 
                               _ptr(info), _ptr(ws), ws.numel() * ws.element_size(), _stream(z.device)),
            "whs_backward")
     return (grad_x if need_x else None), (grad_lambda if need_lambda else None), info
+
+
+def whs_gcv(x: torch.Tensor, w: torch.Tensor, grid: torch.Tensor, d: int, P: int | None = None,
+            lambda_best=None, scores=None, info=None, want_scores: bool = False, workspace=None):
+    """Per-series scalar weight by GCV over ``grid`` (float64 device tensor).
+
+    ``x``: ``(nb, T, 1, S)``.  Returns ``(lambda_best (P,), scores (P, n_grid) or None, info)``.
+    """
+    _need_gpu(x, w, grid, lambda_best, scores, info, workspace)
+    nb, T, C, S, P = _geometry(x, P)
+    if C != 1:
+        raise ValueError("GCV works on one band")
+    if grid.dtype != torch.float64 or grid.dim() != 1:
+        raise TypeError("grid must be a 1-D float64 device tensor")
+    desc = make_desc(P, T, d, 1, S, _dtype_code(x), WHS_LAMBDA_SCALAR)
+    if lambda_best is None:
+        lambda_best = torch.empty(P, dtype=x.dtype, device=x.device)
+    if want_scores and scores is None:
+        scores = torch.empty((P, grid.numel()), dtype=torch.float64, device=x.device)
+    if info is None:
+        info = torch.empty(P, dtype=torch.int32, device=x.device)
+    n = int(lib().whs_gcv_workspace_bytes(ctypes.byref(desc)))
+    ws = workspace if workspace is not None else torch.empty(max(n, 8), dtype=torch.uint8, device=x.device)
+    _check(lib().whs_gcv(ctypes.byref(desc), _ptr(w), _ptr(x), _ptr(grid), int(grid.numel()), _ptr(lambda_best),
+                         _ptr(scores), _ptr(info), _ptr(ws), ws.numel() * ws.element_size(), _stream(x.device)),
+           "whs_gcv")
+    return lambda_best, scores, info
+
+
+class Plan:
+    """Uneven batch (groups of equal length and order) solved in one persistent launch.
+
+    ``groups``: list of dicts with keys ``n_series, T, d, x_off, w_off,
+    lam_off, info_off`` (element offsets into flat buffers, interleave 64).
+    """
+
+    def __init__(self, groups, dtype=torch.float32, per_diff: bool = False):
+        n = len(groups)
+        arr = (WhsGroup * n)(*[WhsGroup(int(g["n_series"]), int(g["T"]), int(g["d"]), int(g["x_off"]),
+                                        int(g["w_off"]), int(g["lam_off"]), int(g["info_off"])) for g in groups])
+        self.groups = [dict(g) for g in groups]
+        self.dtype = dtype
+        self._h = ctypes.c_void_p()
+        code = WHS_F64 if dtype == torch.float64 else WHS_F32
+        kind = WHS_LAMBDA_PER_DIFF if per_diff else WHS_LAMBDA_SCALAR
+        _check(lib().whs_plan_create(ctypes.byref(self._h), arr, n, 1, code, kind, 64), "whs_plan_create")
+
+    def _args(self, w, lam, x, z):
+        _need_gpu(w, lam, x, z)
+        for t in (lam, x, z):
+            if t.dtype != self.dtype:
+                raise TypeError("plan buffers must have the plan's storage dtype")
+        return _ptr(w), _ptr(lam), _ptr(x), _ptr(z)
+
+    def solve(self, w, lam, x, z, info=None):
+        a = self._args(w, lam, x, z)
+        _check(lib().whs_plan_solve(self._h, *a, _ptr(info), _stream(x.device)), "whs_plan_solve")
+        return z
+
+    def graph_launch(self, w, lam, x, z, info=None):
+        a = self._args(w, lam, x, z)
+        _check(lib().whs_plan_graph_launch(self._h, *a, _ptr(info), _stream(x.device)), "whs_plan_graph_launch")
+        return z
+
+    def autotune(self, w, lam, x, z, force: bool = False):
+        a = self._args(w, lam, x, z)
+        _check(lib().whs_plan_autotune(self._h, *a, int(bool(force)), _stream(x.device)), "whs_plan_autotune")
+        return self.config()
+
+    def config(self) -> dict:
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().whs_plan_config(self._h, *[ctypes.byref(t) for t in v]), "whs_plan_config")
+        return {"tile_profile": v[0].value, "waves_per_block": v[1].value, "waves_per_simd": v[2].value,
+                "n_items": v[3].value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().whs_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class WhittakerFn(torch.autograd.Function):

@@ -111,3 +111,33 @@ def test_binding_refuses_cpu_tensors():
     w = torch.zeros((1, 10, 64), dtype=torch.uint8)
     with pytest.raises(ValueError):
         whs.whs_solve(x, w, torch.ones(64), 2)
+
+
+def test_gcv_validation():
+    L = whs.lib()
+    g = ctypes.c_void_p(1 << 20)
+    desc = whs.make_desc(10, 50, 2, 2, 64, 0, 0)        # two bands: unsupported
+    assert L.whs_gcv(ctypes.byref(desc), FAKE, FAKE, g, 21, FAKE, None, None, FAKE, 1 << 30, None) == -2
+    desc = whs.make_desc(10, 50, 2, 1, 32, 0, 0)        # interleave not a multiple of 64
+    assert L.whs_gcv(ctypes.byref(desc), FAKE, FAKE, g, 21, FAKE, None, None, FAKE, 1 << 30, None) == -2
+    desc = whs.make_desc(10, 50, 2, 1, 64, 0, 1)        # lambda_best is scalar per series
+    assert L.whs_gcv(ctypes.byref(desc), FAKE, FAKE, g, 21, FAKE, None, None, FAKE, 1 << 30, None) == -2
+    desc = whs.make_desc(10, 50, 2, 1, 64, 0, 0)
+    assert L.whs_gcv(ctypes.byref(desc), FAKE, FAKE, g, 0, FAKE, None, None, FAKE, 1 << 30, None) == -1
+    assert L.whs_gcv(ctypes.byref(desc), FAKE, FAKE, g, 21, FAKE, None, None, None, 0, None) == -4
+    assert L.whs_gcv_workspace_bytes(ctypes.byref(desc)) > 0
+
+
+def test_plan_validation():
+    L = whs.lib()
+    h = ctypes.c_void_p()
+    g = (whs.WhsGroup * 1)(whs.WhsGroup(10, 50, 2, 0, 0, 0, 0))
+    assert L.whs_plan_create(ctypes.byref(h), g, 1, 2, 0, 0, 64) == -2      # several bands
+    assert L.whs_plan_create(ctypes.byref(h), g, 1, 1, 0, 0, 32) == -2      # interleave != 64
+    assert L.whs_plan_create(ctypes.byref(h), g, 0, 1, 0, 0, 64) == -1      # no groups
+    bad = (whs.WhsGroup * 1)(whs.WhsGroup(10, 2, 2, 0, 0, 0, 0))            # T <= d
+    assert L.whs_plan_create(ctypes.byref(h), bad, 1, 1, 0, 0, 64) == -1
+    bad = (whs.WhsGroup * 1)(whs.WhsGroup(10, 50, 5, 0, 0, 0, 0))           # order 5
+    assert L.whs_plan_create(ctypes.byref(h), bad, 1, 1, 0, 0, 64) == -2
+    assert L.whs_plan_solve(None, FAKE, FAKE, FAKE, FAKE, None, None) == -1
+    assert L.whs_plan_config(None, None, None, None, None) == -1

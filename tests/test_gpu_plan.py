@@ -1,0 +1,115 @@
+"""GPU parity of the uneven-batch plan: one persistent launch over groups of
+different length and order, its HIP graph replay, and its autotuner."""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import whs_ref as R
+from paper_2604_00048_amd import synth, whs
+from tests._cases import assert_solution
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(37, 1, 5), (37, 3, 64), (100, 2, 150), (100, 4, 70), (365, 1, 129), (365, 2, 1), (365, 3, 65)]
+
+
+def _groups(dtype):
+    r = np.random.default_rng(11)
+    out = []
+    for T, d, n in SHAPES:
+        x = r.normal(size=(n, T, 1)) * 0.1 + 0.3
+        p = r.uniform(0.05, 0.3, size=(n, 1))
+        w = (r.random((n, T)) < p).astype(np.uint8)
+        w[:, ::max(T // (d + 2), 1)] = 1
+        lam = 10.0 ** r.uniform(-1, 5 if d <= 2 else 3, size=n)
+        x = np.where(w[:, :, None] != 0, x, 0.0)
+        b = synth.Batch(torch.tensor(x).to(dtype).double(), torch.tensor(w), torch.tensor(lam).to(dtype).double(), d)
+        out.append(((T, d), b))
+    return out
+
+
+@pytest.fixture(scope="module")
+def f32_case():
+    g = _groups(torch.float32)
+    x, w, lam, descs = synth.pack_groups(g, dtype=torch.float32, device="cuda")
+    return g, x, w, lam, descs
+
+
+def test_plan_matches_oracle_per_group(f32_case):
+    g, x, w, lam, descs = f32_case
+    plan = whs.Plan(descs, torch.float32)
+    z = torch.zeros_like(x)
+    info = torch.full((sum(d["n_series"] for d in descs),), -1, dtype=torch.int32, device="cuda")
+    plan.solve(w, lam, x, z, info)
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all()
+    for ((T, d), b), desc in zip(g, descs):
+        zn = synth.unpack_group(z, desc).cpu().double().numpy()
+        xn = b.x.numpy()
+        zref, _ = R.solve_band(xn, b.w.numpy(), b.lam.numpy(), d)
+        assert_solution(zn, zref, xn, b.w.numpy(), b.lam.numpy(), d, f64=False)
+    # the plan equals one whs_solve per group, bit for bit
+    for ((T, d), b), desc in zip(g, descs):
+        xi = synth.pack_series(b.x.to(torch.float32), 64).cuda()
+        wi = synth.pack_rows(b.w, 64).cuda()
+        zi, _ = whs.whs_solve(xi, wi, b.lam.to(torch.float32).cuda(), d, b.P)
+        assert torch.equal(synth.unpack_series(zi, b.P), synth.unpack_group(z, desc))
+
+
+def test_graph_replay_matches_eager(f32_case):
+    g, x, w, lam, descs = f32_case
+    plan = whs.Plan(descs, torch.float32)
+    z0 = torch.zeros_like(x)
+    plan.solve(w, lam, x, z0)
+    for k in range(3):
+        z = torch.full_like(x, float("nan"))
+        plan.graph_launch(w, lam, x, z)
+        junk = torch.randn(1 << 20, device="cuda").sum()  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        for desc in descs:
+            assert torch.equal(synth.unpack_group(z, desc), synth.unpack_group(z0, desc)), k
+        del junk
+
+
+def test_autotuner_choices_give_identical_results(f32_case, tmp_path):
+    g, x, w, lam, descs = f32_case
+    os.environ["WHS_TUNE_CACHE"] = str(tmp_path / "tune.txt")
+    try:
+        plan = whs.Plan(descs, torch.float32)
+        z0 = torch.zeros_like(x)
+        plan.solve(w, lam, x, z0)
+        cfg = plan.autotune(w, lam, x, torch.zeros_like(x), force=True)
+        assert cfg["tile_profile"] in (0, 1, 2) and cfg["waves_per_block"] in (1, 2, 4)
+        z1 = torch.zeros_like(x)
+        plan.solve(w, lam, x, z1)
+        torch.cuda.synchronize()
+        for desc in descs:
+            assert torch.equal(synth.unpack_group(z1, desc), synth.unpack_group(z0, desc))
+        assert (tmp_path / "tune.txt").exists()
+        plan2 = whs.Plan(descs, torch.float32)      # picks the cached choice at creation
+        assert plan2.config() == cfg
+    finally:
+        os.environ.pop("WHS_TUNE_CACHE", None)
+
+
+def test_plan_f64_per_difference():
+    r = np.random.default_rng(3)
+    groups = []
+    for T, d, n in [(80, 2, 70), (50, 1, 10), (120, 3, 64)]:
+        x = r.normal(size=(n, T, 1))
+        w = (r.random((n, T)) < 0.3).astype(np.uint8)
+        w[:, ::max(T // (d + 2), 1)] = 1
+        lam = 10.0 ** r.uniform(0, 3, size=(n, T - d))
+        x = np.where(w[:, :, None] != 0, x, 0.0)
+        groups.append(((T, d), synth.Batch(torch.tensor(x), torch.tensor(w), torch.tensor(lam), d)))
+    x, w, lam, descs = synth.pack_groups(groups, dtype=torch.float64, device="cuda")
+    plan = whs.Plan(descs, torch.float64, per_diff=True)
+    z = plan.solve(w, lam, x, torch.zeros_like(x))
+    torch.cuda.synchronize()
+    for ((T, d), b), desc in zip(groups, descs):
+        zn = synth.unpack_group(z, desc).cpu().numpy()
+        zref, _ = R.solve_band(b.x.numpy(), b.w.numpy(), b.lam.numpy(), d)
+        assert_solution(zn, zref, b.x.numpy(), b.w.numpy(), b.lam.numpy(), d, f64=True)
