@@ -42,15 +42,14 @@ def test_gcv_failed_series_and_ties():
     x, w, _ = random_case(P, T, d, per_diff=False, seed=5)
     w[3] = 0
     w[3, 10] = 1                      # one observation: singular for every weight
-    t = np.arange(T) / T
-    x[7, :, 0] = np.where(w[7] != 0, 0.2 + 0.5 * t, 0.0)   # a line: RSS = 0 everywhere, ties
+    x[7, :, 0] = 0.0                  # z = 0 exactly: every score is exactly 0, a true tie
     grid = R.gcv_grid()
     xt, wt, _ = to_device(x, w, np.ones(P), 64, torch.float64)
     lb, sc, info = whs.whs_gcv(xt, wt, torch.tensor(grid, device="cuda"), d, P, want_scores=True)
     torch.cuda.synchronize()
     lb = lb.cpu().numpy()
     assert np.isnan(lb[3]) and info.cpu().numpy()[3] > 0
-    assert lb[7] == grid[0]
-    ref_l, ref_i, _ = R.gcv_select(x[:, :, 0], w, grid, d)
+    assert (sc.cpu().numpy()[7] == 0).all() and lb[7] == grid[0]
+    ref_l, ref_i, ref_s = R.gcv_select(x[:, :, 0], w, grid, d)
     keep = np.arange(P) != 3
     np.testing.assert_array_equal(lb[keep], ref_l[keep])
