@@ -8,7 +8,7 @@ times (Sec. II-C, Sec. IV-B), bounded by a final sigmoid between a minimum
 and a maximum (Sec. IV-B), trained by masking observed times and taking the
 MSE on them (Sec. IV-C).  The network here is a small 1-D convolution stack
 (4 layers, kernel 9, 64 channels, ReLU, "same" zero padding) mapping
-(standardised x, w) over time to a per-day value h; the head maps
+(standardised x, w, day-of-year harmonics) over time to a per-day value h; the head maps
 ``log10 lambda = lo + (hi - lo) sigmoid(h)``.
 
 Precision follows the kernels: weights and stored activations are rounded to
@@ -25,7 +25,7 @@ import numpy as np
 
 K = 9
 PAD = 4
-WIDTHS = (2, 64, 64, 64, 1)
+WIDTHS = (8, 64, 64, 64, 1)
 
 
 def bf16_round(a) -> np.ndarray:
@@ -88,40 +88,45 @@ def init_params(rng: np.random.Generator, widths=WIDTHS):
     return params
 
 
-def forward(params, x_in: np.ndarray):
+def _id(a):
+    return np.asarray(a, dtype=np.float64)
+
+
+def forward(params, x_in: np.ndarray, rounding: bool = True):
     """Network forward with the kernels' rounding points.
 
     ``x_in``: ``(B, T, 2)`` already bfloat16-valued.  Returns ``(h, acts)``:
     ``h`` ``(B, T)`` FP32-valued output of the last layer and ``acts`` the
     stored bfloat16 activations (inputs of every layer).
     """
+    rnd = bf16_round if rounding else _id
     acts = [x_in]
     a = x_in
     n = len(params)
     for i, (W, b) in enumerate(params):
-        Wb = bf16_round(W)
-        y = conv1d_same(a, Wb, b)
+        y = conv1d_same(a, rnd(W), b)
         if i < n - 1:
-            a = bf16_round(np.maximum(y, 0.0))
+            a = rnd(np.maximum(y, 0.0))
             acts.append(a)
         else:
-            h = y[:, :, 0].astype(np.float32).astype(np.float64)
+            h = y[:, :, 0].astype(np.float32).astype(np.float64) if rounding else y[:, :, 0]
     return h, acts
 
 
-def backward(params, acts, gh: np.ndarray):
+def backward(params, acts, gh: np.ndarray, rounding: bool = True):
     """Gradients of the parameters from ``dL/dh`` (``(B, T)``), FP64 sums of
     bfloat16 stored values; the gradient flowing between layers is rounded to
     bfloat16 where the kernels store it."""
+    rnd = bf16_round if rounding else _id
     grads = [None] * len(params)
-    g = gh[:, :, None]
+    g = rnd(gh)[:, :, None]   # the head's gradient is stored in bfloat16
     for i in range(len(params) - 1, -1, -1):
         W, b = params[i]
         gW, gb = conv1d_wgrad(acts[i], g)
         grads[i] = (gW, gb)
         if i > 0:
-            gx = conv1d_dgrad(g, bf16_round(W))
-            g = bf16_round(gx * (acts[i] > 0))   # ReLU of the layer that produced acts[i]
+            gx = conv1d_dgrad(g, rnd(W))
+            g = rnd(gx * (acts[i] > 0))   # ReLU of the layer that produced acts[i]
     return grads
 
 
@@ -168,9 +173,29 @@ def adam_step(p: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, step: 
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def standardize(x: np.ndarray, w: np.ndarray, mean: float, sd: float) -> np.ndarray:
-    """Network input ``(B, T, 2)``: standardised x at observed times (0 elsewhere) and w,
-    rounded to bfloat16 (Sec. IV-C standardises the spectral values)."""
+def time_features(T: int, start_year: int = 2016) -> np.ndarray:
+    """Per-day time encoding ``(T, 4)``: sine and cosine of the first two
+    harmonics of the day of year (the paper encodes time with sinusoids, Sec. IV-B)."""
+    doy = []
+    y = start_year
+    while len(doy) < T:
+        n = 366 if (y % 4 == 0 and (y % 100 != 0 or y % 400 == 0)) else 365
+        doy.extend(range(n))
+        y += 1
+    a = 2.0 * np.pi * np.asarray(doy[:T], dtype=np.float64) / 365.25
+    return np.stack([np.sin(a), np.cos(a), np.sin(2 * a), np.cos(2 * a)], axis=1)
+
+
+def standardize(x: np.ndarray, w: np.ndarray, mean: float, sd: float, feat: np.ndarray | None = None) -> np.ndarray:
+    """Network input ``(B, T, 8)``: standardised x at observed times (0 elsewhere),
+    w, four time features and two zero channels, rounded to bfloat16
+    (Sec. IV-C standardises the spectral values)."""
     obs = np.asarray(w) != 0
+    B, T = obs.shape
     xs = np.where(obs, (x - mean) / sd, 0.0)
-    return bf16_round(np.stack([xs, obs.astype(np.float64)], axis=-1))
+    f = time_features(T) if feat is None else feat
+    out = np.zeros((B, T, 8))
+    out[:, :, 0] = xs
+    out[:, :, 1] = obs
+    out[:, :, 2:6] = f[None]
+    return bf16_round(out)

@@ -1,0 +1,470 @@
+// Kernels of the weight network g_theta (Sec. II-C, Sec. IV-B): a stack of
+// "same" 1-D convolutions with kernel 9 over time, bfloat16 operands on the
+// matrix cores (v_mfma_f32_16x16x32_bf16) with FP32 accumulation, plus the
+// bounded weight head, the masked MSE gradient and the Adam update.
+//
+// Activations are (P, T, C) bfloat16, channels contiguous, so the im2col row
+// of output time t is the contiguous window x[t-4 .. t+4][0..C).  Weights are
+// (Cout, 9, Cin) bfloat16.  Channel counts are 8, 16 or 64.
+//
+// MFMA 16x16x32 operand layout (checked on the device): lane l holds row
+// l%16 of A and column l%16 of B, with K entries 8*(l/16) .. 8*(l/16)+7; the
+// accumulator lane l holds rows 4*(l/16) .. +3 of column l%16.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "whs_net.h"
+
+namespace whsnet {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+
+constexpr int KT = 9;    // taps
+constexpr int HALO = 4;  // zero padding on each side
+constexpr int TM = 64;   // output time rows per tile
+
+// float -> bfloat16 bits, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+
+// ---------------------------------------------------------------------------
+// Convolution as implicit GEMM: out[t][n] = sum_{tap,c} Wt[n][tap][c] in[t+tap-4][c]
+// MODE 0: + bias, ReLU, bfloat16 out (P,T,NOUT)
+// MODE 1: + bias, FP32 out of channel 0 only (P,T)            (last layer)
+// MODE 2: no bias, out *= (mask > 0), bfloat16 out (P,T,NOUT) (input gradient)
+// One workgroup = 64 time rows of one series; wave w computes output
+// channels 16w..16w+15 for all 64 rows (4 accumulator tiles).
+// ---------------------------------------------------------------------------
+template <int CIN, int NOUT, int MODE>
+__global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wt,
+                                              const float* __restrict__ bias, const uint16_t* __restrict__ mask,
+                                              void* __restrict__ out, int T, int ntiles) {
+  constexpr int KTOT = KT * CIN;
+  constexpr int NS = (KTOT + 31) / 32;      // K steps of 32
+  constexpr int ROWS = TM + 2 * HALO;       // input window rows
+  constexpr int RS = CIN + 8;               // LDS row stride in bf16 (16-byte pad)
+  __shared__ __attribute__((aligned(16))) uint16_t win[ROWS * RS];
+  __shared__ __attribute__((aligned(16))) uint16_t otile[TM * (NOUT + 8)];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4;   // K group of this lane
+  const int r16 = lane & 15;
+  const int64_t p = blockIdx.x / ntiles;
+  const int t0 = (int)(blockIdx.x - p * ntiles) * TM;
+  const uint16_t* inp = in + p * (int64_t)T * CIN;
+
+  // weights of this wave's 16 output channels, all K steps, in registers
+  bf16x8 wb[NS];
+  const int n = wave * 16 + r16;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int k = 32 * s + 8 * g;
+    const int tap = k / CIN, c = k % CIN;
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (tap < KT) v = *reinterpret_cast<const u32x4*>(wt + ((int64_t)n * KT + tap) * CIN + c);
+    wb[s] = __builtin_bit_cast(bf16x8, v);
+  }
+  // input window rows t0-4 .. t0+67 (zero outside 0..T-1), 16-byte chunks
+  constexpr int CH = CIN / 8;
+  for (int i = threadIdx.x; i < ROWS * CH; i += blockDim.x) {
+    const int r = i / CH, c8 = i % CH;
+    const int t = t0 - HALO + r;
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (t >= 0 && t < T) v = *reinterpret_cast<const u32x4*>(inp + (int64_t)t * CIN + 8 * c8);
+    *reinterpret_cast<u32x4*>(win + r * RS + 8 * c8) = v;
+  }
+  __syncthreads();
+
+  f32x4 acc[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int k = 32 * s + 8 * g;
+    const int tap = k / CIN, c = k % CIN;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (tap < KT) v = *reinterpret_cast<const u32x4*>(win + (16 * m + r16 + tap) * RS + c);
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, v), wb[s], acc[m], 0, 0, 0);
+    }
+  }
+
+  // epilogue: lane holds rows 16m + 4g + j, column n
+  const float bv = (MODE != 2 && bias) ? bias[n] : 0.f;
+  if constexpr (MODE == 1) {
+    if (n == 0) {
+      float* o = static_cast<float*>(out) + p * (int64_t)T;
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int t = t0 + 16 * m + 4 * g + j;
+          if (t < T) o[t] = acc[m][j] + bv;
+        }
+    }
+    return;
+  } else {
+    constexpr int OS = NOUT + 8;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 16 * m + 4 * g + j;
+        float v = acc[m][j] + bv;
+        if (MODE == 0) v = v > 0.f ? v : 0.f;
+        otile[row * OS + n] = f2bf(v);
+      }
+    __syncthreads();
+    uint16_t* o = static_cast<uint16_t*>(out) + p * (int64_t)T * NOUT;
+    const uint16_t* mk = mask ? mask + p * (int64_t)T * NOUT : nullptr;
+    constexpr int OCH = NOUT / 8;
+    for (int i = threadIdx.x; i < TM * OCH; i += blockDim.x) {
+      const int r = i / OCH, c8 = i % OCH;
+      const int t = t0 + r;
+      if (t >= T) continue;
+      u32x4 v = *reinterpret_cast<const u32x4*>(otile + r * OS + 8 * c8);
+      if (MODE == 2) {
+        const u32x4 mv = *reinterpret_cast<const u32x4*>(mk + (int64_t)t * NOUT + 8 * c8);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t lo = (mv[q] & 0x7fffu) != 0u && !(mv[q] & 0x8000u) ? 0x0000ffffu : 0u;
+          const uint32_t hi = ((mv[q] >> 16) & 0x7fffu) != 0u && !(mv[q] & 0x80000000u) ? 0xffff0000u : 0u;
+          v[q] &= (lo | hi);
+        }
+      }
+      *reinterpret_cast<u32x4*>(o + (int64_t)t * NOUT + 8 * c8) = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: gW[n][tap][c] = sum_{p,t} gy[p,t,n] in[p,t+tap-4,c],
+// gb[n] = sum gy[p,t,n].  K = time: each step takes 32 time rows of one
+// series, gathers the transposed operands from LDS, and accumulates in
+// registers; workgroup w writes its partial sums to part[w] and
+// k_wgrad_reduce adds them in a fixed order (deterministic).
+// ---------------------------------------------------------------------------
+template <int CIN, int NOUT>
+__global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ in, const uint16_t* __restrict__ gy,
+                                               float* __restrict__ part, int64_t P, int T) {
+  constexpr int NN = KT * CIN;               // GEMM N
+  constexpr int NT = (NN + 15) / 16;         // N tiles of 16
+  constexpr int TK = 32;                     // time rows per step
+  constexpr int XR = TK + 2 * HALO;
+  constexpr int XS = CIN + 2;                // LDS strides in bf16 (odd words: fewer conflicts)
+  constexpr int GS = NOUT + 2;
+  __shared__ uint16_t xt[XR * XS];
+  __shared__ uint16_t gt[TK * GS];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4;
+  const int r16 = lane & 15;
+  const int m = wave * 16 + r16;  // output channel of the A rows
+  const int64_t chunks = (T + TK - 1) / TK;
+  const int64_t items = P * chunks;
+
+  f32x4 acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t p = it / chunks;
+    const int t0 = (int)(it - p * chunks) * TK;
+    const uint16_t* ip = in + p * (int64_t)T * CIN;
+    const uint16_t* gp = gy + p * (int64_t)T * NOUT;
+    __syncthreads();
+    for (int i = threadIdx.x; i < XR * CIN; i += blockDim.x) {
+      const int r = i / CIN, c = i % CIN;
+      const int t = t0 - HALO + r;
+      xt[r * XS + c] = (t >= 0 && t < T) ? ip[(int64_t)t * CIN + c] : (uint16_t)0;
+    }
+    for (int i = threadIdx.x; i < TK * NOUT; i += blockDim.x) {
+      const int r = i / NOUT, c = i % NOUT;
+      const int t = t0 + r;
+      gt[r * GS + c] = (t < T) ? gp[(int64_t)t * NOUT + c] : (uint16_t)0;
+    }
+    __syncthreads();
+    // A: gy^T rows m, K = time 8g .. 8g+7
+    bf16x8 a;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint16_t b = gt[(8 * g + j) * GS + m];
+      a[j] = __builtin_bit_cast(__bf16, b);
+      bsum += bf2f(b);
+    }
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int nn = 16 * q + r16;
+      const int tap = nn / CIN, c = nn % CIN;
+      bf16x8 b;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint16_t v = (nn < NN) ? xt[(8 * g + j + tap) * XS + c] : (uint16_t)0;
+        b[j] = __builtin_bit_cast(__bf16, v);
+      }
+      acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
+    }
+  }
+  // partial sums: part[w][n][nn] (NOUT x NN) then part bias after them
+  float* pw = part + (int64_t)blockIdx.x * (NOUT * NN + NOUT);
+#pragma unroll
+  for (int q = 0; q < NT; ++q)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = wave * 16 + 4 * g + j;  // output channel
+      const int col = 16 * q + r16;           // (tap, c)
+      if (col < NN) pw[row * NN + col] = acc[q][j];
+    }
+  // bias: the four K groups of a channel hold partial sums
+  bsum += __shfl_xor(bsum, 16);
+  bsum += __shfl_xor(bsum, 32);
+  if (g == 0) pw[NOUT * NN + m] = bsum;
+}
+
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int nparts, int len, float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  float s = 0.f;
+  for (int w = 0; w < nparts; ++w) s += part[(int64_t)w * len + i];
+  out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// elementwise kernels
+// ---------------------------------------------------------------------------
+
+// Network input (P, T, 8): x standardised where observed (0 elsewhere), w,
+// then four time features per day (feat: (T, 4)), then two zero channels.
+__global__ void k_net_input(const float* __restrict__ x, const uint8_t* __restrict__ w, int64_t P, int T, int S,
+                            float mean, float inv_sd, const float* __restrict__ feat, uint16_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P * T) return;
+  const int64_t p = i / T;
+  const int t = (int)(i - p * T);
+  const int64_t b = p / S;
+  const int s = (int)(p - b * S);
+  const int64_t off = (b * T + t) * S + s;
+  const bool obs = w[off] != 0;
+  const float xs = obs ? (x[off] - mean) * inv_sd : 0.f;
+  u32x4 v;
+  v[0] = (uint32_t)f2bf(xs) | ((uint32_t)f2bf(obs ? 1.f : 0.f) << 16);
+  v[1] = (uint32_t)f2bf(feat[t * 4 + 0]) | ((uint32_t)f2bf(feat[t * 4 + 1]) << 16);
+  v[2] = (uint32_t)f2bf(feat[t * 4 + 2]) | ((uint32_t)f2bf(feat[t * 4 + 3]) << 16);
+  v[3] = 0u;
+  *reinterpret_cast<u32x4*>(out + i * 8) = v;
+}
+
+__device__ __forceinline__ float sigm(float h) { return 1.f / (1.f + __expf(-h)); }
+
+// Bounded head: log10 lambda = lo + (hi-lo) sigmoid(h) per day; difference row
+// k takes day k + d/2; written in the interleaved per-difference layout.
+__global__ void k_head_fwd(const float* __restrict__ h, int64_t P, int T, int S, int d, float lo, float hi,
+                           float* __restrict__ lam) {
+  const int Td = T - d;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P * Td) return;
+  const int64_t p = i / Td;
+  const int k = (int)(i - p * Td);
+  const float hv = h[p * (int64_t)T + k + d / 2];
+  const float e = lo + (hi - lo) * sigm(hv);
+  const int64_t b = p / S;
+  const int s = (int)(p - b * S);
+  lam[(b * Td + k) * S + s] = exp10f(e);
+}
+
+// dL/dh from dL/dlambda (interleaved) into channel 0 of a (P, T, 16) bfloat16
+// gradient (channels 1..15 zero), the padded output of the last layer.
+__global__ void k_head_bwd(const float* __restrict__ h, const float* __restrict__ glam, int64_t P, int T, int S,
+                           int d, float lo, float hi, uint16_t* __restrict__ gh16) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P * T) return;
+  const int64_t p = i / T;
+  const int t = (int)(i - p * T);
+  const int k = t - d / 2;
+  float g = 0.f;
+  if (k >= 0 && k < T - d) {
+    const int64_t b = p / S;
+    const int s = (int)(p - b * S);
+    const float hv = h[i];
+    const float sg = sigm(hv);
+    const float lamv = exp10f(lo + (hi - lo) * sg);
+    g = glam[(b * (T - d) + k) * S + s] * lamv * 2.302585093f * (hi - lo) * sg * (1.f - sg);
+  }
+  u32x4 z = {0u, 0u, 0u, 0u};
+  u32x4 v = z;
+  v[0] = (uint32_t)f2bf(g);
+  *reinterpret_cast<u32x4*>(gh16 + i * 16) = v;
+  *reinterpret_cast<u32x4*>(gh16 + i * 16 + 8) = z;
+}
+
+// g = 2 (z - x) / n at held-out points (0 elsewhere), and sum of squares into *loss.
+__global__ void k_mse(const float* __restrict__ z, const float* __restrict__ x, const uint8_t* __restrict__ hold,
+                      int64_t n_elem, float inv_n, float* __restrict__ g, double* __restrict__ loss) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float sq = 0.f;
+  if (i < n_elem) {
+    const bool h = hold[i] != 0;
+    const float r = h ? z[i] - x[i] : 0.f;
+    g[i] = 2.f * r * inv_n;
+    sq = r * r;
+  }
+  // wavefront reduction, one atomic per wavefront
+  for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+  if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, (double)sq);
+}
+
+// Adam with bias correction on FP32 master weights (n_out, 9, n_in) of which
+// the first n_real output rows are trained; writes the bfloat16 forward copy
+// (n_out_pad, 9, n_in) and the transposed, tap-flipped copy used by the
+// input gradient (n_in, 9, n_out_pad).
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_pack_weights(const float* __restrict__ w, int n_real, int n_out_pad, int n_in,
+                               uint16_t* __restrict__ wf, uint16_t* __restrict__ wd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = n_out_pad * KT * n_in;
+  if (i >= total) return;
+  const int o = i / (KT * n_in);
+  const int rem = i - o * KT * n_in;
+  const int tap = rem / n_in, c = rem % n_in;
+  const uint16_t b = o < n_real ? f2bf(w[(o * KT + tap) * n_in + c]) : (uint16_t)0;
+  wf[i] = b;
+  if (wd) wd[(c * KT + (KT - 1 - tap)) * n_out_pad + o] = b;
+}
+
+}  // namespace whsnet
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+using namespace whsnet;
+
+namespace {
+int st(hipError_t e) { return e == hipSuccess ? 0 : -3; }
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+bool okc(int c) { return c == 8 || c == 16 || c == 64; }
+}  // namespace
+
+extern "C" {
+
+int whs_net_conv_fwd(const uint16_t* in, int cin, const uint16_t* w, const float* bias, int cout, int mode,
+                     const uint16_t* mask, void* out, int64_t P, int T, void* stream) {
+  if (!in || !w || !out || P < 0 || T < 1 || !okc(cin) || (cout != 16 && cout != 64)) return -1;
+  if (mode < 0 || mode > 2 || (mode == 2 && !mask)) return -1;
+  if (P == 0) return 0;
+  const int ntiles = (int)nblk(T, TM);
+  if (P * ntiles > 0x7fffffffLL) return -2;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  dim3 grid((unsigned)(P * ntiles));
+  dim3 block(cout == 64 ? 256 : 64);
+#define WHS_CONV(CI, CO, MO) \
+  hipLaunchKernelGGL((k_conv<CI, CO, MO>), grid, block, 0, s, in, w, bias, mask, out, T, ntiles)
+  if (cin == 8 && cout == 64 && mode == 0) WHS_CONV(8, 64, 0);
+  else if (cin == 64 && cout == 64 && mode == 0) WHS_CONV(64, 64, 0);
+  else if (cin == 64 && cout == 16 && mode == 1) WHS_CONV(64, 16, 1);
+  else if (cin == 64 && cout == 64 && mode == 2) WHS_CONV(64, 64, 2);
+  else if (cin == 16 && cout == 64 && mode == 2) WHS_CONV(16, 64, 2);
+  else return -2;
+#undef WHS_CONV
+  return st(hipGetLastError());
+}
+
+size_t whs_net_wgrad_workspace_bytes(int cin, int cout, int parts) {
+  return (size_t)parts * ((size_t)cout * KT * cin + cout) * sizeof(float);
+}
+
+int whs_net_conv_wgrad(const uint16_t* in, int cin, const uint16_t* gy, int cout, float* grad, float* ws,
+                       size_t ws_bytes, int parts, int64_t P, int T, void* stream) {
+  if (!in || !gy || !grad || !ws || P < 1 || T < 1 || parts < 1 || !okc(cin) ||
+      (cout != 16 && cout != 64))
+    return -1;
+  if (ws_bytes < whs_net_wgrad_workspace_bytes(cin, cout, parts)) return -4;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  dim3 block(cout == 64 ? 256 : 64);
+  if (cin == 8 && cout == 64) hipLaunchKernelGGL((k_wgrad<8, 64>), dim3(parts), block, 0, s, in, gy, ws, P, T);
+  else if (cin == 64 && cout == 64) hipLaunchKernelGGL((k_wgrad<64, 64>), dim3(parts), block, 0, s, in, gy, ws, P, T);
+  else if (cin == 64 && cout == 16) hipLaunchKernelGGL((k_wgrad<64, 16>), dim3(parts), block, 0, s, in, gy, ws, P, T);
+  else return -2;
+  const int len = cout * KT * cin + cout;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(len, 256)), dim3(256), 0, s, ws, parts, len, grad);
+  return st(hipGetLastError());
+}
+
+int whs_net_input(const float* x, const uint8_t* w, int64_t P, int T, int S, float mean, float inv_sd,
+                  const float* feat, uint16_t* out, void* stream) {
+  if (!x || !w || !feat || !out || P < 0 || T < 1 || S < 1) return -1;
+  if (P == 0) return 0;
+  hipLaunchKernelGGL(k_net_input, dim3(nblk(P * T, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), x, w, P,
+                     T, S, mean, inv_sd, feat, out);
+  return st(hipGetLastError());
+}
+
+int whs_net_head_fwd(const float* h, int64_t P, int T, int S, int d, float lo, float hi, float* lam, void* stream) {
+  if (!h || !lam || P < 0 || T <= d || d < 1 || S < 1) return -1;
+  if (P == 0) return 0;
+  hipLaunchKernelGGL(k_head_fwd, dim3(nblk(P * (T - d), 256)), dim3(256), 0, static_cast<hipStream_t>(stream), h,
+                     P, T, S, d, lo, hi, lam);
+  return st(hipGetLastError());
+}
+
+int whs_net_head_bwd(const float* h, const float* glam, int64_t P, int T, int S, int d, float lo, float hi,
+                     uint16_t* gh16, void* stream) {
+  if (!h || !glam || !gh16 || P < 0 || T <= d || d < 1 || S < 1) return -1;
+  if (P == 0) return 0;
+  hipLaunchKernelGGL(k_head_bwd, dim3(nblk(P * T, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), h, glam, P,
+                     T, S, d, lo, hi, gh16);
+  return st(hipGetLastError());
+}
+
+int whs_net_mse(const float* z, const float* x, const uint8_t* hold, int64_t n_elem, float inv_n, float* g,
+                double* loss, void* stream) {
+  if (!z || !x || !hold || !g || n_elem < 0) return -1;
+  if (n_elem == 0) return 0;
+  hipLaunchKernelGGL(k_mse, dim3(nblk(n_elem, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), z, x, hold,
+                     n_elem, inv_n, g, loss);
+  return st(hipGetLastError());
+}
+
+int whs_net_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                 int step, void* stream) {
+  if (!p || !g || !m || !v || n < 0 || step < 1) return -1;
+  if (n == 0) return 0;
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(nblk(n, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), p, g, m, v, n, lr,
+                     b1, b2, eps, c1, c2);
+  return st(hipGetLastError());
+}
+
+int whs_net_pack_weights(const float* w, int n_real, int n_out_pad, int n_in, uint16_t* wf, uint16_t* wd,
+                         void* stream) {
+  if (!w || !wf || n_real < 1 || n_out_pad < n_real || n_in < 1) return -1;
+  const int total = n_out_pad * KT * n_in;
+  hipLaunchKernelGGL(k_pack_weights, dim3(nblk(total, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), w,
+                     n_real, n_out_pad, n_in, wf, wd);
+  return st(hipGetLastError());
+}
+
+}  // extern "C"

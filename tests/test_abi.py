@@ -23,12 +23,17 @@ def test_library_built():
 
 
 def test_every_declared_symbol_is_exported():
+    from paper_2604_00048_amd import net
     L = whs.lib()
     names = _declared("whs.h")
-    assert {"whs_solve", "whs_backward", "whs_factor", "whs_status_str"} <= set(names)
+    assert {"whs_solve", "whs_backward", "whs_factor", "whs_status_str", "whs_gcv", "whs_plan_create"} <= set(names)
     for n in names:
         assert hasattr(L, n), n
         assert n in whs.SIGNATURES, f"binding lacks {n}"
+    for n in _declared("whs_net.h"):
+        assert hasattr(L, n), n
+        assert n in net.NET_SIGNATURES, f"binding lacks {n}"
+    net.lib()  # every signature binds
 
 
 def test_status_strings_and_version():

@@ -1,0 +1,177 @@
+"""GPU parity of the weight-network kernels against the FP64 reference on the
+same bfloat16 inputs: stored bfloat16 results within one bfloat16 ulp, FP32
+accumulations within 1e-5 relative, the whole network within rounding."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import convnet_ref as N
+from paper_2604_00048_amd import net, synth
+
+pytestmark = pytest.mark.gpu
+rng = np.random.default_rng(42)
+dev = "cuda"
+
+
+def to_bf(a) -> torch.Tensor:
+    """float64 array -> device bfloat16 bits (int16 tensor)."""
+    return torch.tensor(np.asarray(a), dtype=torch.float32).to(torch.bfloat16).view(torch.int16).to(dev)
+
+
+def from_bf(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().view(torch.bfloat16).to(torch.float64).numpy()
+
+
+def ulp_diff(a: np.ndarray, b: np.ndarray) -> int:
+    """Largest distance in bfloat16 steps between same-shaped bfloat16-valued arrays."""
+    def key(x):
+        u = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).view(torch.int16).to(torch.int32).numpy()
+        return np.where(u < 0, -(u & 0x7FFF), u)
+    return int(np.abs(key(a) - key(b)).max())
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+P, T = 3, 150   # three tiles of 64 rows with a ragged tail
+
+
+@pytest.mark.parametrize("cin", [8, 64])
+def test_conv_forward_relu(cin):
+    x = N.bf16_round(rng.normal(size=(P, T, cin)) if cin == 8 else np.abs(rng.normal(size=(P, T, cin))))
+    W = N.bf16_round(rng.normal(size=(64, 9, cin)) * 0.2)
+    b = rng.normal(size=64).astype(np.float32).astype(np.float64)
+    out = torch.empty((P, T, 64), dtype=torch.int16, device=dev)
+    net.conv_fwd(to_bf(x), cin, to_bf(W), torch.tensor(b, dtype=torch.float32, device=dev), 64, 0, None, out, P, T)
+    ref = N.bf16_round(np.maximum(N.conv1d_same(x, W, b), 0.0))
+    assert ulp_diff(from_bf(out), ref) <= 1
+
+
+def test_conv_last_layer_fp32():
+    x = N.bf16_round(np.abs(rng.normal(size=(P, T, 64))))
+    W = np.zeros((16, 9, 64))
+    W[0] = N.bf16_round(rng.normal(size=(9, 64)) * 0.1)
+    b = np.zeros(16)
+    b[0] = 0.25
+    h = torch.empty((P, T), dtype=torch.float32, device=dev)
+    net.conv_fwd(to_bf(x), 64, to_bf(W), torch.tensor(b, dtype=torch.float32, device=dev), 16, 1, None, h, P, T)
+    ref = N.conv1d_same(x, W[:1], b[:1])[:, :, 0]
+    assert rel(h.cpu().double().numpy(), ref) < 1e-5
+
+
+@pytest.mark.parametrize("cin_g", [64, 16])
+def test_conv_input_gradient_masked(cin_g):
+    # gradient of a layer with 64 inputs and cin_g (padded) outputs
+    gy = N.bf16_round(rng.normal(size=(P, T, cin_g)))
+    W = N.bf16_round(rng.normal(size=(cin_g, 9, 64)) * 0.2)   # layer weights (out, tap, in)
+    act = N.bf16_round(np.maximum(rng.normal(size=(P, T, 64)), 0.0))
+    Wd = np.transpose(W[:, ::-1, :], (2, 1, 0)).copy()         # (in, tap, out), taps flipped
+    out = torch.empty((P, T, 64), dtype=torch.int16, device=dev)
+    net.conv_fwd(to_bf(gy), cin_g, to_bf(Wd), None, 64, 2, to_bf(act), out, P, T)
+    ref = N.bf16_round(N.conv1d_dgrad(gy, W) * (act > 0))
+    assert ulp_diff(from_bf(out), ref) <= 1
+
+
+@pytest.mark.parametrize("cin,cout", [(8, 64), (64, 64), (64, 16)])
+def test_weight_gradient(cin, cout):
+    x = N.bf16_round(rng.normal(size=(P, T, cin)))
+    gy = N.bf16_round(rng.normal(size=(P, T, cout)))
+    grad = torch.empty(cout * 9 * cin + cout, dtype=torch.float32, device=dev)
+    net.conv_wgrad(to_bf(x), cin, to_bf(gy), cout, grad, P, T, parts=7)
+    gW, gb = N.conv1d_wgrad(x, gy)
+    g = grad.cpu().double().numpy()
+    assert rel(g[:cout * 9 * cin].reshape(cout, 9, cin), gW) < 1e-5
+    assert rel(g[cout * 9 * cin:], gb) < 1e-5
+
+
+def test_packed_weight_copies():
+    W = rng.normal(size=(1, 9, 64)).astype(np.float32)
+    wf = torch.empty(16 * 9 * 64, dtype=torch.int16, device=dev)
+    wd = torch.empty(64 * 9 * 16, dtype=torch.int16, device=dev)
+    net._chk(net.lib().whs_net_pack_weights(net._p(torch.tensor(W.reshape(-1), device=dev)), 1, 16, 64,
+                                            net._p(wf), net._p(wd), net._s(torch.device(dev))), "pack")
+    f = from_bf(wf).reshape(16, 9, 64)
+    d = from_bf(wd).reshape(64, 9, 16)
+    Wb = N.bf16_round(W.astype(np.float64))
+    np.testing.assert_array_equal(f[0], Wb[0])
+    assert (f[1:] == 0).all()
+    np.testing.assert_array_equal(d[:, :, 0], Wb[0][::-1].T)
+
+
+def test_elementwise_kernels():
+    S, d, Pn, Tn = 64, 2, 70, 97
+    x = rng.normal(size=(Pn, Tn)) * 0.1 + 0.3
+    w = (rng.random((Pn, Tn)) < 0.3).astype(np.uint8)
+    xi = synth.pack_series(torch.tensor(x[:, :, None], dtype=torch.float32), S).to(dev)
+    wi = synth.pack_rows(torch.tensor(w), S).to(dev)
+    feat = net.time_features(Tn).to(dev)
+    x8 = net.net_input(xi, wi, Pn, Tn, S, 0.3, 0.1, feat)
+    ref = N.standardize(x.astype(np.float32).astype(np.float64), w, 0.3, 1 / np.float32(1 / 0.1), N.time_features(Tn))
+    assert ulp_diff(from_bf(x8), ref) <= 1
+    h = rng.normal(size=(Pn, Tn)) * 2
+    ht = torch.tensor(h, dtype=torch.float32, device=dev)
+    lam = net.head_fwd(ht, Pn, Tn, S, d)
+    lam_ref = N.head_rows(N.head(h.astype(np.float32).astype(np.float64)), d)
+    got = synth.unpack_rows(lam.cpu(), Pn).double().numpy()
+    assert np.max(np.abs(got / lam_ref - 1)) < 1e-5
+    glam = rng.normal(size=(Pn, Tn - d))
+    gl = synth.pack_rows(torch.tensor(glam, dtype=torch.float32), S).to(dev)
+    gh16 = net.head_bwd(ht, gl, Pn, Tn, S, d)
+    gh = from_bf(gh16)
+    assert (gh[:, :, 1:] == 0).all()
+    gh_ref = N.head_backward(h.astype(np.float32).astype(np.float64), glam.astype(np.float32).astype(np.float64), d)
+    assert ulp_diff(gh[:, :, 0], N.bf16_round(gh_ref)) <= 1
+    z = torch.tensor(rng.normal(size=(1000,)), dtype=torch.float32, device=dev)
+    xx = torch.tensor(rng.normal(size=(1000,)), dtype=torch.float32, device=dev)
+    hold = torch.tensor(rng.random(1000) < 0.2, dtype=torch.uint8, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    nh = int(hold.sum())
+    g = net.mse(z, xx, hold, 1.0 / nh, loss=loss)
+    L, gref = N.masked_mse(z.cpu().double().numpy(), xx.cpu().double().numpy(), hold.cpu().numpy())
+    assert abs(loss.item() / nh - L) < 1e-5 * L
+    assert rel(g.cpu().double().numpy(), gref) < 1e-6
+
+
+def test_adam_kernel():
+    n = 1000
+    p0 = rng.normal(size=n).astype(np.float32)
+    p = torch.tensor(p0, device=dev)
+    m = torch.zeros(n, device=dev)
+    v = torch.zeros(n, device=dev)
+    q, mq, vq = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+    for step in range(1, 4):
+        g = rng.normal(size=n).astype(np.float32)
+        net._chk(net.lib().whs_net_adam(net._p(p), net._p(torch.tensor(g, device=dev)), net._p(m), net._p(v), n,
+                                        1e-3, 0.9, 0.999, 1e-8, step, net._s(torch.device(dev))), "adam")
+        q, mq, vq = N.adam_step(q, g.astype(np.float64), mq, vq, step, 1e-3)
+    assert np.abs(p.cpu().double().numpy() - q).max() < 1e-6
+
+
+def test_whole_network_forward_backward():
+    Pn, Tn = 2, 130
+    model = net.ConvNet(dev, seed=3)
+    params = []
+    for i, (cin, co, cop) in enumerate(net.LAYERS):
+        flat = model.master[i].cpu().double().numpy()
+        W = flat[:co * 9 * cin].reshape(co, 9, cin)
+        b = flat[co * 9 * cin:] + 0.05 * rng.normal(size=co)
+        model.master[i][co * 9 * cin:] = torch.tensor(b, dtype=torch.float32)
+        params.append((W, b.astype(np.float32).astype(np.float64)))
+    model.pack()
+    x8 = N.bf16_round(np.concatenate([rng.normal(size=(Pn, Tn, 6)), np.zeros((Pn, Tn, 2))], axis=2))
+    h = model.forward(to_bf(x8), Pn, Tn)
+    h_ref, acts = N.forward(params, x8)
+    assert rel(h.cpu().double().numpy(), h_ref) < 1e-2
+    gh = rng.normal(size=(Pn, Tn))
+    gh16 = np.zeros((Pn, Tn, 16))
+    gh16[:, :, 0] = gh
+    model.backward(to_bf(gh16), Pn, Tn)
+    grads = N.backward(params, acts, gh)
+    for i, (cin, co, cop) in enumerate(net.LAYERS):
+        g = model.grad[i].cpu().double().numpy()
+        gw = g[:cop * 9 * cin].reshape(cop, 9, cin)[:co]
+        gb = g[cop * 9 * cin:cop * 9 * cin + co]
+        assert rel(gw, grads[i][0]) < 2e-2, i
+        assert rel(gb, grads[i][1]) < 2e-2, i
