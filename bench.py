@@ -96,19 +96,138 @@ def cpu_baseline(pk, d: int, n_sample: int, workers: int):
     return done / dt, dt, len(jobs)
 
 
+def _events(n):
+    import torch
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def bench_multiband(args):
+    """Homoscedastic, ten bands sharing one factor, forward solve."""
+    import torch
+    from paper_2604_00048_amd import synth, whs
+    dev = torch.device("cuda:0")
+    dtype = torch.float64 if args.dtype == "f64" else torch.float32
+    P, T, C, d, S = args.P, args.T, 10, 2, args.interleave
+    pk = synth.generate_packed("multiband", P, S=S, dtype=dtype, device=dev, chunk=8192, T=T, C=C)
+    z = torch.empty_like(pk.x)
+    info = torch.empty(P, dtype=torch.int32, device=dev)
+    desc = whs.make_desc(P, T, d, C, S, whs.WHS_F64 if dtype == torch.float64 else whs.WHS_F32, whs.WHS_LAMBDA_SCALAR)
+    ws = torch.empty(whs.workspace_bytes(desc), dtype=torch.uint8, device=dev)
+    for _ in range(args.warmup):
+        whs.whs_solve(pk.x, pk.w, pk.lam, d, P, z=z, info=info, workspace=ws)
+    torch.cuda.synchronize()
+    e0, e1 = _events(2)
+    e0.record()
+    for _ in range(args.steps):
+        whs.whs_solve(pk.x, pk.w, pk.lam, d, P, z=z, info=info, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    esz = 8 if dtype == torch.float64 else 4
+    fb, _ = alg_bytes(T, d, C, esz, False)
+    gbs = fb * P / (ms * 1e-3) / 1e9
+    return {
+        "metric": "series/sec (T=3288,d=2,C=10 forward)", "value": P / (ms * 1e-3), "unit": "series/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"homoscedastic smoother forward: P={P}, T={T}, d=2, C=10 bands sharing one factor, "
+                               f"scalar lambda, {args.dtype.upper()} storage / FP64 arithmetic",
+                   "P": P, "T": T, "d": d, "C": C, "storage": args.dtype},
+        "roofline": {"bound": "hbm", "kernel": "whs_solve", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": gbs / PEAK_HBM_GBS, "traffic": None, "alg_bytes_per_series": fb, "ms_per_launch": ms},
+        "failed_series": int((info != 0).sum().item()),
+    }
+
+
+def bench_uneven(args):
+    """Uneven lengths and orders in one persistent launch, replayed from a HIP graph."""
+    import torch
+    from paper_2604_00048_amd import synth, whs
+    dev = torch.device("cuda:0")
+    groups = synth.uneven_groups(n_series=args.n_uneven, device=dev)
+    x, w, lam, descs = synth.pack_groups(groups, dtype=torch.float32, device=dev)
+    z = torch.empty_like(x)
+    N = sum(d_["n_series"] for d_ in descs)
+    info = torch.empty(N, dtype=torch.int32, device=dev)
+    plan = whs.Plan(descs, torch.float32)
+    cfg = plan.autotune(w, lam, x, z, force=args.retune)
+    for _ in range(args.warmup):
+        plan.graph_launch(w, lam, x, z, info)
+    torch.cuda.synchronize()
+    e0, e1 = _events(2)
+    e0.record()
+    for _ in range(args.steps):
+        plan.graph_launch(w, lam, x, z, info)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    alg = sum(d_["n_series"] * (4 * d_["T"] + d_["T"] + 4 + 4 * d_["T"]) for d_ in descs)
+    gbs = alg / (ms * 1e-3) / 1e9
+    longest = max(d_["T"] for d_ in descs)
+    return {
+        "metric": "series/sec (uneven T in {365,730,1461,3288}, d in {1,2,3}, forward, one persistent launch)",
+        "value": N / (ms * 1e-3), "unit": "series/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"uneven batch: {N} series, T in {{365,730,1461,3288}}, d in {{1,2,3}}, scalar "
+                               f"lambda, FP32 storage, HIP-graph replay of one persistent launch",
+                   "n_series": N, "groups": len(descs), "plan": cfg, "longest_T": longest},
+        "roofline": {"bound": "hbm", "kernel": "whs_plan", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": gbs / PEAK_HBM_GBS, "traffic": None, "alg_bytes": alg, "ms_per_launch": ms},
+        "failed_series": int((info != 0).sum().item()),
+    }
+
+
+def bench_learned(args):
+    """Learned per-day weights vs the GCV-chosen scalar weight, held-out RMSE and throughput."""
+    import torch
+    from paper_2604_00048_amd import learned
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    L = learned.train(dev, steps=args.train_steps, batch_size=4096, lr=args.lr,
+                      log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    ev = learned.evaluate(L, dev, n_series=args.eval_series)
+    return {
+        "metric": "held-out RMSE (learned per-day lambda vs GCV scalar lambda), T=3288, d=2",
+        "value": ev["rmse_learned"], "unit": "reflectance RMSE", "n_gpus": 1, "steps": args.train_steps,
+        "warmup": 0, "ms_per_step": t_train / max(args.train_steps, 1) * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
+        "config": {"workload": f"learned weights: 4-layer conv net (kernel 9, 64 channels, BF16 MFMA) trained "
+                               f"{args.train_steps} steps of 4096 series through the smoother, evaluated on "
+                               f"{args.eval_series} fresh series against GCV over 21 scalar weights",
+                   "train_steps": args.train_steps, "lr": args.lr},
+        "heldout": ev,
+        "train_seconds": t_train,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--P", type=int, default=65536)
+    ap.add_argument("--workload", default="hetero", choices=["hetero", "multiband", "uneven", "learned"])
+    ap.add_argument("--P", type=int, default=None)
     ap.add_argument("--T", type=int, default=3288)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--interleave", type=int, default=64)
+    ap.add_argument("--n-uneven", type=int, default=100000)
+    ap.add_argument("--retune", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval-series", type=int, default=262144)
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 256 MiB three times (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (pixels shard across GPUs "
+                                   "with no exchange, see the design notes)"}), flush=True)
+        sys.exit(2)
 
     if args.calibrate_copy:
         import torch
@@ -121,18 +240,28 @@ def main():
         print(json.dumps({"calibration": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}))
         return
 
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (pixels shard across GPUs "
-                                   "with no exchange, see the design notes)"}), flush=True)
-        sys.exit(2)
-
     import torch
-
-    from paper_2604_00048_amd import synth, whs
-
+    from paper_2604_00048_amd import whs
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
     whs.lib()
+    if args.workload == "multiband":
+        args.P = args.P or 262144
+        print(json.dumps(bench_multiband(args)), flush=True)
+        return
+    if args.workload == "uneven":
+        print(json.dumps(bench_uneven(args)), flush=True)
+        return
+    if args.workload == "learned":
+        print(json.dumps(bench_learned(args)), flush=True)
+        return
+    args.P = args.P or 65536
+    print(json.dumps(bench_hetero(args)), flush=True)
+
+
+def bench_hetero(args):
+    import torch
+    from paper_2604_00048_amd import synth, whs
+    dev = torch.device("cuda:0")
     d, S, P, T = 2, args.interleave, args.P, args.T
     t_gen = time.perf_counter()
     pk = synth.generate_packed("heteroscedastic", P, S=S, dtype=torch.float32, device=dev, chunk=8192, T=T)
@@ -231,7 +360,7 @@ def main():
             "sample": f"{n} of the {P} series (first ones), FP64 numpy banded LDL^T forward + adjoint, "
                       f"{used} processes, {secs:.1f} s",
         }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -1,0 +1,147 @@
+"""Training and evaluation of the learned-weight form against the plain form.
+
+Learned form (Sec. II-C, Sec. IV-B, Sec. IV-C): per-day weights from the
+network, one weight per difference row, trained end to end through the
+smoother by hiding 10 % of the observed points of every series and taking
+the MSE on them.  Plain form: one scalar weight per series chosen by GCV over
+a grid.  Both forms see the same inputs (held-out points removed) and are
+scored on the same held-out points of fresh series.
+
+Every numerical step runs in the library's kernels; this module draws the
+synthetic batches, allocates tensors and orders the calls.
+"""
+
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import torch
+
+from . import net, synth, whs
+
+D = 2
+S = 64
+T_DAYS = 3288
+GRID = [10.0 ** (-1.0 + 0.3 * i) for i in range(21)]
+
+
+@dataclass
+class Batch:
+    P: int
+    x_train: torch.Tensor   # interleaved (nb, T, 1, S) FP32, held-out points removed
+    w_train: torch.Tensor   # interleaved (nb, T, S) uint8
+    x_true: torch.Tensor    # interleaved observations (targets at held-out points)
+    hold: torch.Tensor      # interleaved held-out mask
+    n_hold: int
+
+
+def make_batch(P: int, seed: int, chunk: int, device, T: int = T_DAYS, frac: float = 0.1) -> Batch:
+    """One batch of the nine-year daily generator (band 0), with a held-out split."""
+    b = synth.multiband_homoscedastic(P, T=T, C=1, d=D, seed=seed, device=device, chunk=chunk)
+    gen = synth._gen(seed * 7 + chunk * 13 + 1, device)
+    hold = synth.holdout_split(b.w, frac, gen)
+    w_tr = (b.w != 0) & (hold == 0)
+    x_tr = torch.where(w_tr[:, :, None], b.x, torch.zeros((), dtype=b.x.dtype, device=b.x.device))
+    return Batch(P=P,
+                 x_train=synth.pack_series(x_tr.float(), S),
+                 w_train=synth.pack_rows(w_tr.to(torch.uint8), S),
+                 x_true=synth.pack_series(b.x.float(), S),
+                 hold=synth.pack_rows(hold, S),
+                 n_hold=int(hold.sum().item()))
+
+
+def input_stats(batch: Batch):
+    """Global mean and sd of the observed training values (Sec. IV-C standardises the values)."""
+    m = batch.w_train != 0
+    v = batch.x_train[:, :, 0, :][m].double()
+    return float(v.mean()), float(v.std())
+
+
+class Learned:
+    """The network plus the statistics and scratch tensors of one batch size."""
+
+    def __init__(self, device, mean: float, sd: float, seed: int = 0):
+        self.device = torch.device(device)
+        self.model = net.ConvNet(self.device, seed=seed)
+        self.mean, self.sd = mean, sd
+        self.feat = net.time_features(T_DAYS).to(self.device)
+
+    def weights(self, batch: Batch, keep: bool = False):
+        """h and the per-difference weights of a batch."""
+        x8 = net.net_input(batch.x_train, batch.w_train, batch.P, T_DAYS, S, self.mean, self.sd, self.feat)
+        h = self.model.forward(x8, batch.P, T_DAYS, keep=keep)
+        lam = net.head_fwd(h, batch.P, T_DAYS, S, D)
+        return h, lam
+
+    def train_step(self, batch: Batch, lr: float) -> float:
+        h, lam = self.weights(batch, keep=True)
+        z, info = whs.whs_solve(batch.x_train, batch.w_train, lam, D, batch.P)
+        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        # MSE in standardised units: (z - x)^2 / sd^2 averaged over held-out points
+        g = net.mse(z, batch.x_true, batch.hold, 1.0 / (max(batch.n_hold, 1) * self.sd ** 2), loss=loss)
+        _, glam, _ = whs.whs_backward(batch.w_train, lam, z, g, D, batch.P, need_x=False)
+        gh16 = net.head_bwd(h, glam, batch.P, T_DAYS, S, D)
+        self.model.backward(gh16, batch.P, T_DAYS)
+        self.model.adam(lr)
+        return loss.item() / max(batch.n_hold, 1) / self.sd ** 2
+
+
+def heldout_sse(z: torch.Tensor, batch: Batch) -> float:
+    loss = torch.zeros(1, dtype=torch.float64, device=z.device)
+    net.mse(z, batch.x_true, batch.hold, 1.0, loss=loss)
+    return loss.item()
+
+
+def train(device, steps: int = 400, batch_size: int = 4096, lr: float = 1e-3, seed: int = 2604004805,
+          log=None) -> Learned:
+    """Train the network end to end through the smoother (Adam; cosine-decayed learning rate)."""
+    first = make_batch(batch_size, seed, 0, device)
+    mean, sd = input_stats(first)
+    L = Learned(device, mean, sd)
+    for s in range(steps):
+        b = first if s == 0 else make_batch(batch_size, seed, s, device)
+        lr_s = lr * 0.5 * (1.0 + math.cos(math.pi * s / steps))
+        loss = L.train_step(b, lr_s)
+        if log and (s % 50 == 0 or s == steps - 1):
+            log(f"step {s} loss {loss:.4f} lr {lr_s:.2e}")
+    return L
+
+
+def evaluate(L: Learned, device, n_series: int = 262144, chunk: int = 16384, seed: int = 2604004806):
+    """Held-out RMSE (data units) and throughput of the learned and the plain forms on fresh series."""
+    grid = torch.tensor(GRID, dtype=torch.float64, device=device)
+    sse_l = sse_p = 0.0
+    n = 0
+    t_l = t_p = 0.0
+    lam_dev = []
+    for i, p0 in enumerate(range(0, n_series, chunk)):
+        P = min(chunk, n_series - p0)
+        b = make_batch(P, seed, i, device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, lam = L.weights(b)
+        z_l, _ = whs.whs_solve(b.x_train, b.w_train, lam, D, P)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lam_best, _, _ = whs.whs_gcv(b.x_train, b.w_train, grid, D, P)
+        z_p, _ = whs.whs_solve(b.x_train, b.w_train, lam_best, D, P)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_l += t1 - t0
+        t_p += t2 - t1
+        sse_l += heldout_sse(z_l, b)
+        sse_p += heldout_sse(z_p, b)
+        n += b.n_hold
+        lam_dev.append(torch.log10(lam_best.double()).mean().item())
+    return {
+        "n_series": n_series,
+        "heldout_points": n,
+        "rmse_learned": math.sqrt(sse_l / n),
+        "rmse_plain_gcv": math.sqrt(sse_p / n),
+        "gain": 1.0 - math.sqrt(sse_l / n) / math.sqrt(sse_p / n),
+        "series_per_s_learned": n_series / t_l,
+        "series_per_s_plain_gcv": n_series / t_p,
+        "mean_log10_lambda_gcv": sum(lam_dev) / len(lam_dev),
+    }
