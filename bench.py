@@ -258,6 +258,25 @@ def main():
     print(json.dumps(bench_hetero(args)), flush=True)
 
 
+def copy_ceiling(dev, nbytes: int = 2 << 30, reps: int = 5) -> float:
+    """Read+write GB/s of a plain device-to-device copy: the practical HBM ceiling on this GPU."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def bench_hetero(args):
     import torch
     from paper_2604_00048_amd import synth, whs
@@ -307,6 +326,7 @@ def bench_hetero(args):
     ms_step = total_ms / K
     n_fail = int((info != 0).sum().item())
 
+    copy_gbs = copy_ceiling(dev)
     fb, bb = alg_bytes(T, d, 1, 4, True)
     bwd_gbs = bb * P / (bwd_ms * 1e-3) / 1e9
     fwd_gbs = fb * P / (fwd_ms * 1e-3) / 1e9
@@ -341,6 +361,7 @@ def bench_hetero(args):
             "traffic": traffic,
             "alg_bytes_per_series": bb,
             "ms_per_launch": bwd_ms,
+            "copy_GBps": copy_gbs,
         },
         "kernels": {
             "whs_solve": {"ms": fwd_ms, "alg_GBps": fwd_gbs, "frac": fwd_gbs / PEAK_HBM_GBS,

@@ -381,6 +381,23 @@ def selinv_band(Lrow: np.ndarray, Dp: np.ndarray) -> np.ndarray:
     return S
 
 
+def posterior_variance(w: np.ndarray, lam, d: int):
+    """Diagonal of ``Omega^{-1}`` for every series: the pointwise posterior
+    variance of ``z`` in units of the observation noise variance (the
+    credibility band of Sec. IV-D, Fig. 4, is ``z`` plus or minus a multiple of
+    its square root times the noise level).  Taken from the selected inverse of
+    the banded LDL^T factor.  Returns ``(var, info)`` with ``var`` of shape
+    ``(P, T)``; failed series are NaN.
+    """
+    w = np.asarray(w)
+    AB = omega_band(w, lam, d)
+    Lrow, Dp, info = ldl_band(AB)
+    info = structural_info(w, d, info)
+    var = selinv_band(Lrow, Dp)[:, 0, :].copy()
+    var[info != 0] = np.nan
+    return var, info
+
+
 def gcv_scores(x: np.ndarray, w: np.ndarray, grid, d: int):
     """Generalised cross-validation for each scalar weight in ``grid``.
 

@@ -483,3 +483,67 @@ def test_gcv_prefers_heavy_smoothing_on_noise_around_a_line():
     x = np.where(w != 0, 0.1 + 0.001 * np.arange(T) + 0.05 * r.normal(size=(4, T)), 0.0)
     lam_best, idx, _ = R.gcv_select(x, w, R.gcv_grid(), d)
     assert (lam_best >= 1e3).all()
+
+
+# --- posterior variance (diagonal of Omega^{-1}) ------------------------------------
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+@pytest.mark.parametrize("per_diff", [False, True])
+def test_P13_posterior_variance_is_diagonal_of_dense_inverse(d, per_diff):
+    T = 30
+    _, w, lam = _rand_case(3, T, d, per_diff=per_diff, seed=170 + d)
+    var, info = R.posterior_variance(w, lam, d)
+    assert (info == 0).all()
+    inv = np.linalg.inv(R.omega_dense(w, lam, d))
+    np.testing.assert_allclose(var, np.diagonal(inv, axis1=1, axis2=2), rtol=1e-9)
+
+
+def test_P13_posterior_variance_two_point_closed_form():
+    # d = 1, T = 2, both observed: Omega = [[1+l, -l], [-l, 1+l]], diag of the
+    # inverse = (1+l) / (1+2l)
+    lam = np.array([0.0, 0.5, 3.0, 1e4])
+    w = np.ones((4, 2), np.uint8)
+    var, _ = R.posterior_variance(w, lam, 1)
+    expect = (1 + lam) / (1 + 2 * lam)
+    # the second pivot (1+l) - l^2/(1+l) cancels: relative rounding about l * eps
+    np.testing.assert_allclose(var, np.stack([expect, expect], 1), rtol=4 * (1 + lam.max()) * 2.2e-16)
+
+
+def test_P13_posterior_variance_identity_and_time_reversal():
+    T, d = 25, 3
+    var, _ = R.posterior_variance(np.ones((1, T), np.uint8), np.zeros(1), d)
+    np.testing.assert_array_equal(var, np.ones((1, T)))
+    _, w, lam = _rand_case(2, T, d, per_diff=True, seed=181)
+    w[:, -d - 1:] = 1
+    v, _ = R.posterior_variance(w, lam, d)
+    vr, _ = R.posterior_variance(w[:, ::-1].copy(), lam[:, ::-1].copy(), d)
+    np.testing.assert_allclose(vr[:, ::-1], v, rtol=1e-10)
+
+
+def test_P13_posterior_variance_decreases_with_each_new_observation():
+    T, d = 40, 2
+    _, w, lam = _rand_case(1, T, d, per_diff=True, p_obs=0.2, seed=190)
+    v0, _ = R.posterior_variance(w, lam, d)
+    t = int(np.nonzero(w[0] == 0)[0][len(np.nonzero(w[0] == 0)[0]) // 2])
+    w1 = w.copy()
+    w1[0, t] = 1
+    v1, _ = R.posterior_variance(w1, lam, d)
+    assert (v1 <= v0 * (1 + 1e-12)).all()
+    assert v1[0, t] < v0[0, t] * (1 - 1e-6)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_P13_posterior_variance_heavy_smoothing_is_polynomial_fit_variance(d):
+    # lambda -> inf: z is the least-squares polynomial of degree d-1 through the
+    # observed samples, whose variance at t is phi(t)^T (V^T W V)^{-1} phi(t)
+    T = 24
+    r = np.random.default_rng(200 + d)
+    w = (r.random((1, T)) < 0.5).astype(np.uint8)
+    w[0, :d + 1] = 1
+    var, _ = R.posterior_variance(w, np.array([1e9]), d)
+    tt = (np.arange(T) - T / 2) / T
+    V = np.stack([tt ** k for k in range(d)], 1)
+    G = V.T @ (V * w[0][:, None])
+    expect = np.einsum("tk,kl,tl->t", V, np.linalg.inv(G), V)
+    np.testing.assert_allclose(var[0], expect, rtol=2e-4)
+    assert abs((var[0] * w[0]).sum() - d) < 1e-3
