@@ -151,6 +151,29 @@ int whs_gcv(const whs_desc* desc, const uint8_t* w, const void* x, const double*
             void* stream);
 
 /*
+ * Posterior variance of the smoothed series (Sec. IV-D, Fig. 4: the
+ * credibility band drawn around the reconstruction).
+ *
+ * var[p][t] = (Omega^{-1})[t, t] with Omega = W + D^T Lambda D of eq. (3):
+ * the variance of z_t per unit observation-noise variance, so a band is
+ * z_t +/- k * sigma * sqrt(var_t) for a noise level sigma chosen by the
+ * caller (for instance RSS / (m - ED) with ED = sum_t w_t var_t, the GCV
+ * effective dimension).  Computed from the banded LDL^T factor by the
+ * selected-inverse recurrence, run backwards in time:
+ *   Sigma[t, t+j] = -sum_i L[t+i, t] Sigma[t+i, t+j]   (j = 1..d)
+ *   Sigma[t, t]   = 1/Dp[t] - sum_i L[t+i, t] Sigma[t+i, t].
+ * var: device, storage dtype, series layout with C = 1 (like x); lambda as
+ * in whs_solve (both kinds).  Requires n_rhs == 1 (WHS_ERR_ARG otherwise)
+ * and interleave a multiple of 64 (WHS_ERR_UNSUPPORTED otherwise).  Failed
+ * series (info != 0) get NaN.  All outputs are written on `stream`; the
+ * caller owns every buffer.  The workspace size is
+ * whs_variance_workspace_bytes(desc).
+ */
+size_t whs_variance_workspace_bytes(const whs_desc* desc);
+int whs_variance(const whs_desc* desc, const uint8_t* w, const void* lambda, void* var, int32_t* info,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Uneven batches in one persistent launch.
  *
  * A group is a set of series sharing a length T and an order d, stored in

@@ -168,4 +168,30 @@ int whs_gcv(const whs_desc* desc, const uint8_t* w, const void* x, const double*
   return hip_status(whs::launch_gcv(L, static_cast<hipStream_t>(stream)));
 }
 
+size_t whs_variance_workspace_bytes(const whs_desc* desc) {
+  if (check_desc(desc) != WHS_OK || desc->n_series == 0) return 0;
+  return whs::var_checkpoint_bytes(desc->n_series, desc->interleave, desc->T, desc->d);
+}
+
+int whs_variance(const whs_desc* desc, const uint8_t* w, const void* lambda, void* var, int32_t* info,
+                 void* workspace, size_t workspace_bytes, void* stream) {
+  int st = check_desc(desc);
+  if (st != WHS_OK) return st;
+  if (desc->n_rhs != 1) return WHS_ERR_ARG;
+  if (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31)) return WHS_ERR_UNSUPPORTED;
+  if (desc->n_series == 0) return WHS_OK;
+  if (!w || !lambda || !var) return WHS_ERR_ARG;
+  const size_t e = elem(desc);
+  if (!aligned(lambda, e) || !aligned(var, e) || !aligned(info, 4)) return WHS_ERR_ARG;
+  if (!workspace || workspace_bytes < whs_variance_workspace_bytes(desc) || !aligned(workspace, 8))
+    return WHS_ERR_WORKSPACE;
+  whs::LaunchDesc L = make_launch(desc);
+  L.w = w;
+  L.lam = lambda;
+  L.out = var;
+  L.info = info;
+  L.ws = static_cast<double*>(workspace);
+  return hip_status(whs::launch_var(L, static_cast<hipStream_t>(stream)));
+}
+
 }  // extern "C"

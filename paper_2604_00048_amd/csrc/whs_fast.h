@@ -673,4 +673,177 @@ __global__ __launch_bounds__(256) void k_gcv(GcvArgs a) {
   k.run(a);
 }
 
+
+// ---------------------------------------------------------------------------
+// Posterior variance: the diagonal of Omega^{-1}.
+//
+// Sweep 1 factors the series (no right-hand side: x reads as zero through an
+// empty buffer range) and checkpoints the state as in the solve kernel; the
+// reverse sweep recomputes each tile and runs the same selected-inverse
+// recurrence as the GCV kernel, storing Sigma[t, t] for every t.
+// ---------------------------------------------------------------------------
+
+struct VarArgs {
+  int64_t P;
+  int T, S, nt;
+  const uint8_t* w;
+  const void* lam;
+  void* var;
+  int32_t* info;
+  double* ck;
+};
+
+template <int D, int B, typename TS, bool PERDIFF>
+struct Var : Fast<D, 1, B, TS, false, PERDIFF> {
+  using Base = Fast<D, 1, B, TS, false, PERDIFF>;
+  using typename Base::Tile;
+  static constexpr int NF = Base::NF;
+
+  template <bool FULL>
+  __device__ __forceinline__ void rev_tile_var(const Tile& tl, int t0, const double (&ckv)[NF],
+                                               const double (&lwin)[D + 1], double (&sg)[D + 1][D + 1],
+                                               double (&lcr)[D + 1][D + 1], TS* vb, bool failed) const {
+    State<D, 1> st;
+    this->restore(st, ckv, lwin);
+    double lt[B][D + 1];
+    double id[B];
+#pragma unroll
+    for (int s = 0; s < B; ++s) {
+      const int t = t0 + s;
+      double l[D + 1], dt, invdt, yt[1];
+      this->template step<FULL>(st, tl, s, t, l, dt, invdt, yt);
+      const bool v = FULL || t < this->T;
+#pragma unroll
+      for (int i = 1; i <= D; ++i) lt[s][i] = v ? l[i] : 0.0;
+      id[s] = v ? invdt : 0.0;
+    }
+    const int rows = this->rows_from(t0, this->T);
+    const auto ro = make_rsrc(vb + (int64_t)(rows > 0 ? t0 : 0) * this->S, rows * this->S * Base::ES);
+    const double qnan = __builtin_nan("");
+#pragma unroll
+    for (int s = B - 1; s >= 0; --s) {
+      const int t = t0 + s;
+      double L[D + 1];
+#pragma unroll
+      for (int i = 1; i <= D; ++i)
+        L[i] = (s + i < B) ? lt[s + i < B ? s + i : 0][i] : lcr[s + i - B < 0 ? 0 : s + i - B][i];
+      double sj[D + 1];
+#pragma unroll
+      for (int j = 1; j <= D; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 1; i <= D; ++i) acc = __builtin_fma(-L[i], sg[i - 1][j - 1], acc);
+        sj[j] = acc;
+      }
+      double stt = id[s];
+#pragma unroll
+      for (int i = 1; i <= D; ++i) stt = __builtin_fma(-L[i], sj[i], stt);
+      bstore<TS>(ro, this->lx + (uint32_t)(s * this->S) * Base::ES, from_f64<TS>(failed ? qnan : stt));
+      if (FULL || t < this->T) {
+#pragma unroll
+        for (int a = D - 1; a >= 1; --a)
+#pragma unroll
+          for (int b = D - 1; b >= 1; --b) sg[a][b] = sg[a - 1][b - 1];
+        sg[0][0] = stt;
+#pragma unroll
+        for (int b = 1; b < D; ++b) {
+          sg[0][b] = sj[b];
+          sg[b][0] = sj[b];
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int i = 0; i <= D; ++i) lcr[r][i] = lt[r][i];
+  }
+
+  __device__ void run(const VarArgs& g) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int wave_off = __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
+    const int64_t p0 = (int64_t)blockIdx.x * blockDim.x + wave_off;
+    if (p0 >= g.P) return;
+    const int64_t bidx = p0 / g.S;
+    const int s_in = (int)(p - bidx * g.S);
+    const int T = g.T, nt = g.nt;
+    this->T = T;
+    this->S = g.S;
+    this->Ctot = 1;
+    this->c0 = 0;
+    this->nt = nt;
+    this->Rx = 0;  // no right-hand side: every x load is out of range and reads zero
+    this->wb = g.w + bidx * T * g.S;
+    this->xb = reinterpret_cast<const TS*>(this->wb);
+    this->lb = PERDIFF ? static_cast<const TS*>(g.lam) + bidx * (T - D) * g.S : nullptr;
+    this->zb = nullptr;
+    this->ob = nullptr;
+    this->gb = nullptr;
+    this->ckb = g.ck + bidx * nt * NF * g.S;
+    this->accum = false;
+    const bool live = p < g.P;
+    constexpr uint32_t kDead = 0x80000000u;
+    this->lx = live ? (uint32_t)s_in * Base::ES : kDead;
+    this->lw = live ? (uint32_t)s_in : kDead;
+    this->lc = live ? (uint32_t)s_in * 8u : kDead;
+    this->lam_scalar = (!PERDIFF && live) ? to_f64(static_cast<const TS*>(g.lam)[p]) : 0.0;
+    TS* vb = static_cast<TS*>(g.var) + bidx * T * g.S;
+
+    State<D, 1> st;
+    st.zero();
+    int nobs = 0, bad_tile = -1;
+    Tile A, Bt;
+    this->template load_tile<false>(A, 0);
+    for (int j = 0; j < nt; j += 2) {
+      this->template load_tile<false>(Bt, (j + 1) * B);
+      this->store_ck(st, j);
+      bool ok = this->full_tile(j * B) ? this->template fwd_tile<true>(st, A, j * B, nobs)
+                                       : this->template fwd_tile<false>(st, A, j * B, nobs);
+      if (!ok && bad_tile < 0) bad_tile = j;
+      this->template load_tile<false>(A, (j + 2) * B);
+      if (j + 1 < nt) {
+        this->store_ck(st, j + 1);
+        ok = this->full_tile((j + 1) * B) ? this->template fwd_tile<true>(st, Bt, (j + 1) * B, nobs)
+                                          : this->template fwd_tile<false>(st, Bt, (j + 1) * B, nobs);
+        if (!ok && bad_tile < 0) bad_tile = j + 1;
+      }
+    }
+    int info = 0;
+    if (live && bad_tile >= 0) info = this->first_bad_pivot((bad_tile + 1) * B);
+    if (info == 0 && nobs < D) info = T;
+    if (live && g.info) g.info[p] = info;
+    const bool failed = info != 0;
+
+    double sg[D + 1][D + 1], lcr[D + 1][D + 1];
+#pragma unroll
+    for (int i = 0; i <= D; ++i)
+#pragma unroll
+      for (int k = 0; k <= D; ++k) {
+        sg[i][k] = 0.0;
+        lcr[i][k] = 0.0;
+      }
+    double ckA[NF], ckB[NF], lwA[D + 1], lwB[D + 1];
+    int j = nt - 1;
+    this->template load_tile<true>(A, j * B);
+    this->load_ck(j, ckA, lwA);
+    for (; j >= 0; j -= 2) {
+      this->template load_tile<true>(Bt, (j - 1) * B);
+      this->load_ck(j - 1, ckB, lwB);
+      if (this->full_tile(j * B)) rev_tile_var<true>(A, j * B, ckA, lwA, sg, lcr, vb, failed);
+      else rev_tile_var<false>(A, j * B, ckA, lwA, sg, lcr, vb, failed);
+      this->template load_tile<true>(A, (j - 2) * B);
+      this->load_ck(j - 2, ckA, lwA);
+      if (j - 1 >= 0) {
+        if (this->full_tile((j - 1) * B)) rev_tile_var<true>(Bt, (j - 1) * B, ckB, lwB, sg, lcr, vb, failed);
+        else rev_tile_var<false>(Bt, (j - 1) * B, ckB, lwB, sg, lcr, vb, failed);
+      }
+    }
+  }
+};
+
+template <int D, int B, typename TS, bool PERDIFF>
+__global__ __launch_bounds__(256) void k_var(VarArgs a) {
+  Var<D, B, TS, PERDIFF> k;
+  k.run(a);
+}
+
 }  // namespace whs

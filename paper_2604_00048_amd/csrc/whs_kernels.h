@@ -49,3 +49,11 @@ size_t gcv_checkpoint_bytes(int64_t P, int S, int T, int D);
 hipError_t launch_gcv(const GcvLaunch& L, hipStream_t stream);
 
 }  // namespace whs
+
+namespace whs {
+
+// posterior variance: L.out receives diag(Omega^{-1}) in the series layout
+size_t var_checkpoint_bytes(int64_t P, int S, int T, int D);
+hipError_t launch_var(const LaunchDesc& L, hipStream_t stream);
+
+}  // namespace whs

@@ -69,6 +69,8 @@ SIGNATURES = {
     "whs_backward": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "whs_gcv_workspace_bytes": (_SZ, [_DP]),
     "whs_gcv": (ctypes.c_int, [_DP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "whs_variance_workspace_bytes": (_SZ, [_DP]),
+    "whs_variance": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "whs_plan_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(WhsGroup), ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "whs_plan_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -264,6 +266,30 @@ def whs_gcv(x: torch.Tensor, w: torch.Tensor, grid: torch.Tensor, d: int, P: int
                          _ptr(scores), _ptr(info), _ptr(ws), ws.numel() * ws.element_size(), _stream(x.device)),
            "whs_gcv")
     return lambda_best, scores, info
+
+
+def whs_variance(w: torch.Tensor, lam: torch.Tensor, d: int, P: int | None = None, var=None, info=None,
+                 workspace=None):
+    """Posterior variance ``diag(Omega^{-1})`` per series, in the series layout ``(nb, T, 1, S)``.
+
+    Returns ``(var, info)``; ``var`` has the storage dtype of ``lam``.
+    """
+    _need_gpu(w, lam, var, info, workspace)
+    if w.dim() != 3 or w.dtype != torch.uint8:
+        raise ValueError("w must be uint8 of shape (nb, T, S)")
+    nb, T, S = w.shape
+    P = nb * S if P is None else int(P)
+    kind = _lambda_kind(lam, P, nb, T, d, S)
+    desc = make_desc(P, T, d, 1, S, _dtype_code(lam), kind)
+    if var is None:
+        var = torch.empty((nb, T, 1, S), dtype=lam.dtype, device=w.device)
+    if info is None:
+        info = torch.empty(P, dtype=torch.int32, device=w.device)
+    n = int(lib().whs_variance_workspace_bytes(ctypes.byref(desc)))
+    ws = workspace if workspace is not None else torch.empty(max(n, 8), dtype=torch.uint8, device=w.device)
+    _check(lib().whs_variance(ctypes.byref(desc), _ptr(w), _ptr(lam), _ptr(var), _ptr(info), _ptr(ws),
+                              ws.numel() * ws.element_size(), _stream(w.device)), "whs_variance")
+    return var, info
 
 
 class Plan:

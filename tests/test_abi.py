@@ -146,3 +146,19 @@ def test_plan_validation():
     assert L.whs_plan_create(ctypes.byref(h), bad, 1, 1, 0, 0, 64) == -2
     assert L.whs_plan_solve(None, FAKE, FAKE, FAKE, FAKE, None, None) == -1
     assert L.whs_plan_config(None, None, None, None, None) == -1
+
+
+def test_variance_validation():
+    L = whs.lib()
+    desc = whs.make_desc(10, 50, 2, 2, 64, 0, 1)        # one output channel only
+    assert L.whs_variance(ctypes.byref(desc), FAKE, FAKE, FAKE, None, FAKE, 1 << 30, None) == -1
+    desc = whs.make_desc(10, 50, 2, 1, 1, 0, 1)         # interleave not a multiple of 64
+    assert L.whs_variance(ctypes.byref(desc), FAKE, FAKE, FAKE, None, FAKE, 1 << 30, None) == -2
+    desc = whs.make_desc(10, 50, 2, 1, 64, 0, 1)
+    assert L.whs_variance(ctypes.byref(desc), FAKE, None, FAKE, None, FAKE, 1 << 30, None) == -1
+    assert L.whs_variance(ctypes.byref(desc), FAKE, FAKE, FAKE_ODD, None, FAKE, 1 << 30, None) == -1
+    assert L.whs_variance(ctypes.byref(desc), FAKE, FAKE, FAKE, None, None, 0, None) == -4
+    # order 2: 2 + 1 + 2 = 5 doubles per tile of 16 steps per series
+    assert L.whs_variance_workspace_bytes(ctypes.byref(desc)) == ((50 + 15) // 16) * 5 * 64 * 8
+    empty = whs.make_desc(0, 50, 2, 1, 64, 0, 1)
+    assert L.whs_variance(ctypes.byref(empty), None, None, None, None, None, 0, None) == 0
