@@ -12,6 +12,10 @@ Everything here is written from the paper's definitions, slowly and plainly:
 * eq. (2) / eq. (3): ``z = (W + D^T Lambda D)^{-1} W x``; ``Omega`` is the
   matrix in brackets (Sec. III), symmetric positive definite with ``d``
   sub-diagonals.
+* Sec. II, uneven sample times: ``D`` is the discrete derivative of the
+  cited monograph (``d!`` times the divided difference over ``d+1``
+  consecutive times), passed as a ``(T-d, d+1)`` table ``coef`` of row
+  coefficients; every function taking ``coef=None`` uses the daily grid.
 * Fig. 2: lower band storage ``AB[i, t] = Omega[t+i, t]`` with a zero tail.
 * Sec. III-A: Cholesky factorisation, then forward and back substitution.
 * eq. (4) / eq. (5): derivatives w.r.t. the per-row weights and w.r.t. ``x``;
@@ -55,12 +59,37 @@ def diff_coeffs(d: int) -> np.ndarray:
     return np.array([(-1) ** (d - j) * comb(d, j) for j in range(d + 1)], dtype=np.float64)
 
 
-def diff_matrix(T: int, d: int) -> np.ndarray:
-    """Dense ``(T-d) x T`` difference operator ``D`` (Sec. II)."""
+def diff_coeffs_times(times, d: int) -> np.ndarray:
+    """Row coefficients of the order-``d`` discrete derivative on sample times
+    ``t_0 < ... < t_{T-1}`` (Sec. II: the difference operator for unevenly
+    spaced samples of the cited monograph on divided differences, Sec. 6
+    there).  Row ``k`` is ``d!`` times the divided difference over
+    ``t_k..t_{k+d}``:
+    ``c[k, j] = d! / prod_{m != j} (t_{k+j} - t_{k+m})``, ``j = 0..d``.
+    On unit spacing this is ``(-1)^(d-j) C(d, j)``.  Returns ``(T-d, d+1)``.
+    """
+    t = np.asarray(times, dtype=np.float64)
+    T = t.shape[0]
+    fact = float(np.prod(np.arange(1, d + 1)))
+    c = np.zeros((T - d, d + 1))
+    for k in range(T - d):
+        for j in range(d + 1):
+            den = 1.0
+            for m in range(d + 1):
+                if m != j:
+                    den *= t[k + j] - t[k + m]
+            c[k, j] = fact / den
+    return c
+
+
+def diff_matrix(T: int, d: int, coef=None) -> np.ndarray:
+    """Dense ``(T-d) x T`` difference operator ``D`` (Sec. II); ``coef`` is an
+    optional ``(T-d, d+1)`` table of row coefficients (uneven sample times),
+    the daily-grid binomial row otherwise."""
     c = diff_coeffs(d)
     D = np.zeros((T - d, T))
     for k in range(T - d):
-        D[k, k:k + d + 1] = c
+        D[k, k:k + d + 1] = c if coef is None else coef[k]
     return D
 
 
@@ -83,12 +112,12 @@ def lam_rows(lam, P: int, T: int, d: int) -> np.ndarray:
     return lam
 
 
-def omega_dense(w: np.ndarray, lam, d: int) -> np.ndarray:
+def omega_dense(w: np.ndarray, lam, d: int, coef=None) -> np.ndarray:
     """``Omega = W + D^T Lambda D`` as dense ``(P, T, T)`` (eq. (3))."""
     w = np.asarray(w)
     P, T = w.shape
     L = lam_rows(lam, P, T, d)
-    D = diff_matrix(T, d)
+    D = diff_matrix(T, d, coef)
     dt = np.result_type(L.dtype, np.float64)
     out = np.zeros((P, T, T), dtype=dt)
     for p in range(P):
@@ -96,17 +125,18 @@ def omega_dense(w: np.ndarray, lam, d: int) -> np.ndarray:
     return out
 
 
-def omega_band(w: np.ndarray, lam, d: int) -> np.ndarray:
+def omega_band(w: np.ndarray, lam, d: int, coef=None) -> np.ndarray:
     """Lower band storage of ``Omega``: ``AB[p, i, t] = Omega[p, t+i, t]`` (Fig. 2).
 
     Built from ``D^T Lambda D = sum_k lambda_k d_k d_k^T`` (``d_k`` the k-th row
-    of ``D``): row ``k`` adds ``lambda_k c_a c_b`` to ``Omega[k+a, k+b]``.
+    of ``D``): row ``k`` adds ``lambda_k c_a c_b`` to ``Omega[k+a, k+b]``
+    (``c`` the row's coefficients: ``coef[k]`` if given, else the binomial row).
     Entries with ``t+i >= T`` stay zero (the padded tail of Fig. 2).
     """
     w = np.asarray(w)
     P, T = w.shape
     L = lam_rows(lam, P, T, d)
-    c = diff_coeffs(d)
+    c = np.tile(diff_coeffs(d), (T - d, 1)) if coef is None else np.asarray(coef, dtype=np.float64)
     dt = np.result_type(L.dtype, np.float64)
     AB = np.zeros((P, d + 1, T), dtype=dt)
     AB[:, 0, :] += w
@@ -114,7 +144,7 @@ def omega_band(w: np.ndarray, lam, d: int) -> np.ndarray:
     for a in range(d + 1):
         for b in range(a + 1):
             # Omega[k+a, k+b] with a >= b  ->  AB[a-b, k+b]
-            AB[:, a - b, k + b] += L * (c[a] * c[b])
+            AB[:, a - b, k + b] += L * (c[:, a] * c[:, b])
     return AB
 
 
@@ -134,20 +164,20 @@ def band_to_dense(AB: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 
-def solve_dense(x: np.ndarray, w: np.ndarray, lam, d: int) -> np.ndarray:
+def solve_dense(x: np.ndarray, w: np.ndarray, lam, d: int, coef=None) -> np.ndarray:
     """``z = Omega^{-1} W x`` with a dense LU solve (eq. (2) / eq. (3))."""
     x3, squeeze = _as3(x)
     w = np.asarray(w)
-    Om = omega_dense(w, lam, d)
+    Om = omega_dense(w, lam, d, coef)
     rhs = np.where(w[:, :, None] != 0, x3, 0.0)
     z = np.linalg.solve(Om, rhs)
     return z[:, :, 0] if squeeze else z
 
 
-def solve_dense_rhs(b: np.ndarray, w: np.ndarray, lam, d: int) -> np.ndarray:
+def solve_dense_rhs(b: np.ndarray, w: np.ndarray, lam, d: int, coef=None) -> np.ndarray:
     """``v = Omega^{-1} b`` (dense LU), any right-hand side ``b``."""
     b3, squeeze = _as3(b)
-    v = np.linalg.solve(omega_dense(w, lam, d), b3)
+    v = np.linalg.solve(omega_dense(w, lam, d, coef), b3)
     return v[:, :, 0] if squeeze else v
 
 
@@ -218,10 +248,10 @@ def structural_info(w: np.ndarray, d: int, info: np.ndarray) -> np.ndarray:
     return out
 
 
-def solve_band_rhs(b: np.ndarray, w: np.ndarray, lam, d: int):
+def solve_band_rhs(b: np.ndarray, w: np.ndarray, lam, d: int, coef=None):
     """``v = Omega^{-1} b`` by banded LDL^T; returns ``(v, info)``; failed series are NaN."""
     b3, squeeze = _as3(b)
-    AB = omega_band(w, lam, d)
+    AB = omega_band(w, lam, d, coef)
     Lrow, Dp, info = ldl_band(AB)
     info = structural_info(w, d, info)
     v = _subst(Lrow, Dp, b3)
@@ -229,7 +259,7 @@ def solve_band_rhs(b: np.ndarray, w: np.ndarray, lam, d: int):
     return (v[:, :, 0] if squeeze else v), info
 
 
-def solve_band(x: np.ndarray, w: np.ndarray, lam, d: int):
+def solve_band(x: np.ndarray, w: np.ndarray, lam, d: int, coef=None):
     """``z = Omega^{-1} W x`` by banded LDL^T (eq. (3), Sec. III-A); returns ``(z, info)``.
 
     ``x`` is selected where ``w_t = 1``, never multiplied, so its value at
@@ -238,7 +268,7 @@ def solve_band(x: np.ndarray, w: np.ndarray, lam, d: int):
     x3, squeeze = _as3(x)
     w = np.asarray(w)
     rhs = np.where(w[:, :, None] != 0, x3, 0.0)
-    z, info = solve_band_rhs(rhs, w, lam, d)
+    z, info = solve_band_rhs(rhs, w, lam, d, coef)
     return (z[:, :, 0] if squeeze else z), info
 
 
@@ -280,17 +310,18 @@ def cholesky_band(AB: np.ndarray, w: np.ndarray | None = None):
 # ---------------------------------------------------------------------------
 
 
-def apply_D(v: np.ndarray, d: int) -> np.ndarray:
+def apply_D(v: np.ndarray, d: int, coef=None) -> np.ndarray:
     """``(D v)_k`` along axis 1 for ``k = 0..T-d-1``."""
-    c = diff_coeffs(d)
     T = v.shape[1]
+    c = np.tile(diff_coeffs(d), (T - d, 1)) if coef is None else np.asarray(coef, dtype=np.float64)
     out = np.zeros((v.shape[0], T - d) + v.shape[2:], dtype=v.dtype)
     for j in range(d + 1):
-        out = out + c[j] * v[:, j:T - d + j]
+        cj = c[:, j].reshape((1, T - d) + (1,) * (v.ndim - 2))
+        out = out + cj * v[:, j:T - d + j]
     return out
 
 
-def vjp(x: np.ndarray, w: np.ndarray, lam, d: int, g: np.ndarray, z: np.ndarray | None = None):
+def vjp(x: np.ndarray, w: np.ndarray, lam, d: int, g: np.ndarray, z: np.ndarray | None = None, coef=None):
     """Adjoint of ``z = Omega^{-1} W x`` against upstream gradient ``g``.
 
     ``u = Omega^{-1} g``; ``grad_x = W u`` (eq. (5) as a vector-Jacobian
@@ -303,15 +334,15 @@ def vjp(x: np.ndarray, w: np.ndarray, lam, d: int, g: np.ndarray, z: np.ndarray 
     g3, _ = _as3(g)
     w = np.asarray(w)
     if z is None:
-        z3, info = solve_band(x3, w, lam, d)
+        z3, info = solve_band(x3, w, lam, d, coef)
     else:
         z3, _ = _as3(z)
         info = None
-    u, info_u = solve_band_rhs(g3, w, lam, d)
+    u, info_u = solve_band_rhs(g3, w, lam, d, coef)
     if info is None:
         info = info_u
     gx = np.where(w[:, :, None] != 0, u, 0.0)
-    gl = -(apply_D(u, d) * apply_D(z3, d)).sum(axis=2)
+    gl = -(apply_D(u, d, coef) * apply_D(z3, d, coef)).sum(axis=2)
     lam = np.asarray(lam)
     if lam.ndim <= 1:
         gl = gl.sum(axis=1)
@@ -321,18 +352,18 @@ def vjp(x: np.ndarray, w: np.ndarray, lam, d: int, g: np.ndarray, z: np.ndarray 
     return (gx[:, :, 0] if squeeze else gx), gl, info
 
 
-def vjp_dense(x: np.ndarray, w: np.ndarray, lam, d: int, g: np.ndarray):
+def vjp_dense(x: np.ndarray, w: np.ndarray, lam, d: int, g: np.ndarray, coef=None):
     """Same adjoint through explicit dense inverses (tiny T): ``grad_x = W Omega^{-1} g``,
     ``grad_lambda_k = -g^T Omega^{-1} d_k d_k^T z`` (eq. (4), eq. (5))."""
     x3, squeeze = _as3(x)
     g3, _ = _as3(g)
     w = np.asarray(w)
     P, T, C = x3.shape
-    Om = omega_dense(w, lam, d)
+    Om = omega_dense(w, lam, d, coef)
     Oi = np.linalg.inv(Om)
     z = np.einsum("pts,psc->ptc", Oi, np.where(w[:, :, None] != 0, x3, 0.0))
     gx = np.einsum("pts,psc->ptc", Oi, g3) * (w[:, :, None] != 0)
-    D = diff_matrix(T, d)
+    D = diff_matrix(T, d, coef)
     gl = np.zeros((P, T - d))
     for p in range(P):
         for k in range(T - d):
@@ -381,7 +412,7 @@ def selinv_band(Lrow: np.ndarray, Dp: np.ndarray) -> np.ndarray:
     return S
 
 
-def posterior_variance(w: np.ndarray, lam, d: int):
+def posterior_variance(w: np.ndarray, lam, d: int, coef=None):
     """Diagonal of ``Omega^{-1}`` for every series: the pointwise posterior
     variance of ``z`` in units of the observation noise variance (the
     credibility band of Sec. IV-D, Fig. 4, is ``z`` plus or minus a multiple of
@@ -390,7 +421,7 @@ def posterior_variance(w: np.ndarray, lam, d: int):
     ``(P, T)``; failed series are NaN.
     """
     w = np.asarray(w)
-    AB = omega_band(w, lam, d)
+    AB = omega_band(w, lam, d, coef)
     Lrow, Dp, info = ldl_band(AB)
     info = structural_info(w, d, info)
     var = selinv_band(Lrow, Dp)[:, 0, :].copy()

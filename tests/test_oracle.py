@@ -547,3 +547,110 @@ def test_P13_posterior_variance_heavy_smoothing_is_polynomial_fit_variance(d):
     expect = np.einsum("tk,kl,tl->t", V, np.linalg.inv(G), V)
     np.testing.assert_allclose(var[0], expect, rtol=2e-4)
     assert abs((var[0] * w[0]).sum() - d) < 1e-3
+
+
+# --- uneven sample times (Sec. II: divided-difference operator) ----------------------
+
+def _uneven_times(T, seed, step=5.0):
+    """Revisit every ``step`` days with random skipped passes (strictly increasing)."""
+    r = np.random.default_rng(seed)
+    gaps = step * r.integers(1, 4, size=T)
+    return 7.0 + np.cumsum(gaps)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_P14_unit_and_constant_spacing_give_binomial_rows(d):
+    T = 12
+    c1 = R.diff_coeffs_times(np.arange(T) + 40.0, d)
+    np.testing.assert_array_equal(c1, np.tile(R.diff_coeffs(d), (T - d, 1)))
+    c5 = R.diff_coeffs_times(5.0 * np.arange(T), d)
+    np.testing.assert_allclose(c5, np.tile(R.diff_coeffs(d), (T - d, 1)) / 5.0 ** d, rtol=1e-14)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_P14_closed_form_matches_the_recursive_definition(d):
+    # order-k operator = diag(k / (t_{i+k} - t_i)) times the first difference of
+    # the order-(k-1) operator, starting from diag(1 / (t_{i+1} - t_i)) times
+    # the first difference
+    T = 15
+    t = _uneven_times(T, seed=d)
+
+    def first_diff(n):
+        F = np.zeros((n - 1, n))
+        for i in range(n - 1):
+            F[i, i], F[i, i + 1] = -1.0, 1.0
+        return F
+
+    Dk = np.diag(1.0 / (t[1:] - t[:-1])) @ first_diff(T)
+    for k in range(2, d + 1):
+        Dk = np.diag(k / (t[k:] - t[:-k])) @ first_diff(T - k + 1) @ Dk
+    D = R.diff_matrix(T, d, R.diff_coeffs_times(t, d))
+    np.testing.assert_allclose(D, Dk, rtol=1e-10, atol=1e-12 * np.abs(Dk).max())
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_P14_kills_low_degree_polynomials_and_maps_t_to_the_d_to_d_factorial(d):
+    T = 20
+    t = _uneven_times(T, seed=10 + d) / 100.0
+    D = R.diff_matrix(T, d, R.diff_coeffs_times(t, d))
+    for q in range(d):
+        assert np.abs(D @ t ** q).max() < 1e-9 * np.abs(D).max()
+    np.testing.assert_allclose(D @ t ** d, np.full(T - d, float(np.prod(np.arange(1, d + 1)))), rtol=1e-8)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_P14_uneven_smoother_reproduces_low_degree_polynomials(d):
+    T = 40
+    t = _uneven_times(T, seed=20 + d) / 50.0
+    coef = R.diff_coeffs_times(t, d)
+    r = np.random.default_rng(d)
+    w = (r.random((2, T)) < 0.4).astype(np.uint8)
+    w[:, :d + 1] = 1
+    poly = np.polyval(r.normal(size=d), t)            # degree d-1
+    x = np.where(w != 0, poly[None, :], 0.0)
+    z, info = R.solve_band(x, w, np.array([3.0, 300.0]), d, coef)
+    assert (info == 0).all()
+    # exact in exact arithmetic; the bound only absorbs rounding amplified by the
+    # conditioning of Omega (close times give large coefficients)
+    np.testing.assert_allclose(z, np.tile(poly, (2, 1)), rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_P14_uneven_band_solve_and_adjoint_match_dense(d):
+    T = 30
+    t = _uneven_times(T, seed=30 + d)
+    coef = R.diff_coeffs_times(t, d) * 5.0 ** d       # order-one entries
+    x, w, lam = _rand_case(3, T, d, per_diff=True, seed=300 + d)
+    zb, _ = R.solve_band(x, w, lam, d, coef)
+    np.testing.assert_allclose(zb, R.solve_dense(x, w, lam, d, coef), rtol=1e-8, atol=1e-10)
+    g = np.random.default_rng(d).normal(size=x.shape)
+    gx, gl, _ = R.vjp(x, w, lam, d, g, coef=coef)
+    gxd, gld = R.vjp_dense(x, w, lam, d, g, coef=coef)
+    np.testing.assert_allclose(gx, gxd, rtol=1e-8, atol=1e-10)
+    np.testing.assert_allclose(gl, gld, rtol=1e-7, atol=1e-10 * np.abs(gld).max())
+
+
+def test_P14_uneven_time_rescaling_is_absorbed_by_the_weights():
+    # times * s scales row coefficients by s^-d, so lambda * s^(2d) gives the same z
+    T, d, s = 35, 2, 3.7
+    t = _uneven_times(T, seed=41)
+    x, w, lam = _rand_case(2, T, d, per_diff=True, seed=410)
+    z1, _ = R.solve_band(x, w, lam, d, R.diff_coeffs_times(t, d))
+    z2, _ = R.solve_band(x, w, lam * s ** (2 * d), d, R.diff_coeffs_times(s * t, d))
+    np.testing.assert_allclose(z2, z1, rtol=1e-9, atol=1e-12)
+
+
+def test_P14_uneven_grad_lambda_by_finite_differences():
+    T, d = 25, 2
+    t = _uneven_times(T, seed=51)
+    coef = R.diff_coeffs_times(t, d) * 25.0
+    x, w, lam = _rand_case(1, T, d, per_diff=True, seed=510)
+    g = np.random.default_rng(5).normal(size=x.shape)
+    _, gl, _ = R.vjp(x, w, lam, d, g, coef=coef)
+    for k in (0, 7, T - d - 1):
+        h = 1e-6 * lam[0, k]
+        lp, lm = lam.copy(), lam.copy()
+        lp[0, k] += h
+        lm[0, k] -= h
+        fd = (np.sum(g * R.solve_band(x, w, lp, d, coef)[0]) - np.sum(g * R.solve_band(x, w, lm, d, coef)[0])) / (2 * h)
+        assert abs(fd - gl[0, k]) <= 1e-5 * abs(fd) + 1e-6 * np.abs(gl).max(), (k, fd, gl[0, k])
