@@ -151,6 +151,34 @@ int whs_gcv(const whs_desc* desc, const uint8_t* w, const void* x, const double*
             void* stream);
 
 /*
+ * Uneven sample times (Sec. II): when the T samples sit at times
+ * t_0 < t_1 < ... < t_{T-1} (days, any unit) rather than on a daily grid,
+ * D is the order-d discrete derivative of the cited monograph on divided
+ * differences: d! times the divided difference over d+1 consecutive times,
+ *     (D v)_k = sum_{j=0..d} c[k][j] v_{k+j},
+ *     c[k][j] = d! / prod_{m != j} (t_{k+j} - t_{k+m}),   k = 0..T-d-1.
+ * On unit spacing c[k][j] = (-1)^(d-j) C(d, j), the daily-grid operator.
+ * One time axis serves the whole batch (a tile's acquisition calendar);
+ * each series still has its own weights w (clouds, padding) and lambda.
+ *
+ * whs_diff_coef fills coef (device FP64, row-major (T-d) x (d+1)) from
+ * times (device FP64[T]); rows whose times are not strictly increasing or
+ * not finite are NaN (every solve that uses them then fails with info > 0).
+ * whs_solve_coef / whs_backward_coef are whs_solve / whs_backward (fused
+ * path, no factor argument) with Omega = W + D^T Lambda D built from coef.
+ * They require interleave a multiple of 64 (WHS_ERR_UNSUPPORTED otherwise)
+ * and use the whs_workspace_bytes(desc) workspace.  Return codes, info,
+ * aliasing and NaN conventions are those of whs_solve / whs_backward.
+ */
+int whs_diff_coef(const double* times, int32_t T, int32_t d, double* coef, void* stream);
+int whs_solve_coef(const whs_desc* desc, const double* coef, const uint8_t* w, const void* lambda,
+                   const void* x, void* z, int32_t* info, void* workspace, size_t workspace_bytes,
+                   void* stream);
+int whs_backward_coef(const whs_desc* desc, const double* coef, const uint8_t* w, const void* lambda,
+                      const void* z, const void* g, void* grad_x, void* grad_lambda, int32_t* info,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Posterior variance of the smoothed series (Sec. IV-D, Fig. 4: the
  * credibility band drawn around the reconstruction).
  *

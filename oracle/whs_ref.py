@@ -484,12 +484,12 @@ def gcv_select(x: np.ndarray, w: np.ndarray, grid, d: int):
 # ---------------------------------------------------------------------------
 
 
-def backward_error(x: np.ndarray, w: np.ndarray, lam, d: int, z: np.ndarray) -> np.ndarray:
+def backward_error(x: np.ndarray, w: np.ndarray, lam, d: int, z: np.ndarray, coef=None) -> np.ndarray:
     """Componentwise backward error ``max_t |Omega z - W x|_t / (|Omega||z| + |W x|)_t`` per series."""
     x3, _ = _as3(np.asarray(x, dtype=np.float64))
     z3, _ = _as3(np.asarray(z, dtype=np.float64))
     w = np.asarray(w)
-    AB = omega_band(w, lam, d)
+    AB = omega_band(w, lam, d, coef)
     P, dp1, T = AB.shape
     b = np.where(w[:, :, None] != 0, x3, 0.0)
     r = -b.copy()

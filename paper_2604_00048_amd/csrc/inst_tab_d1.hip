@@ -1,0 +1,9 @@
+// Instantiations of the two-sweep kernels on uneven sample times: order d = 1.
+#include "whs_two_sweep.h"
+
+namespace whs {
+hipError_t run_solve_tab_d1(const LaunchDesc& L, hipStream_t stream) { return run_mode_tab_d<1, Mode::Solve>(L, stream); }
+hipError_t run_backward_tab_d1(const LaunchDesc& L, hipStream_t stream) {
+  return run_mode_tab_d<1, Mode::Backward>(L, stream);
+}
+}  // namespace whs

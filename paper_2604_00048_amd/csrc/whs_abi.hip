@@ -131,6 +131,62 @@ int whs_backward(const whs_desc* desc, const uint8_t* w, const void* lambda, con
   return hip_status(whs::launch_backward(L, static_cast<hipStream_t>(stream)));
 }
 
+int whs_diff_coef(const double* times, int32_t T, int32_t d, double* coef, void* stream) {
+  if (d < 1 || T <= d) return d > kMaxD ? WHS_ERR_UNSUPPORTED : WHS_ERR_ARG;
+  if (d > kMaxD) return WHS_ERR_UNSUPPORTED;
+  if (!times || !coef || !aligned(times, 8) || !aligned(coef, 8)) return WHS_ERR_ARG;
+  return hip_status(whs::launch_diff_coef(times, T, d, coef, static_cast<hipStream_t>(stream)));
+}
+
+int whs_solve_coef(const whs_desc* desc, const double* coef, const uint8_t* w, const void* lambda, const void* x,
+                   void* z, int32_t* info, void* workspace, size_t workspace_bytes, void* stream) {
+  int st = check_desc(desc);
+  if (st != WHS_OK) return st;
+  if (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31)) return WHS_ERR_UNSUPPORTED;
+  if (desc->n_series == 0) return WHS_OK;
+  if (!coef || !w || !lambda || !x || !z) return WHS_ERR_ARG;
+  const size_t e = elem(desc);
+  if (!aligned(coef, 8) || !aligned(x, e) || !aligned(z, e) || !aligned(lambda, e) || !aligned(info, 4))
+    return WHS_ERR_ARG;
+  if (!workspace || workspace_bytes < whs_workspace_bytes(desc) || !aligned(workspace, 8)) return WHS_ERR_WORKSPACE;
+  whs::LaunchDesc L = make_launch(desc);
+  L.coef = coef;
+  L.w = w;
+  L.lam = lambda;
+  L.rhs = x;
+  L.out = z;
+  L.info = info;
+  L.ws = static_cast<double*>(workspace);
+  return hip_status(whs::launch_solve(L, static_cast<hipStream_t>(stream)));
+}
+
+int whs_backward_coef(const whs_desc* desc, const double* coef, const uint8_t* w, const void* lambda, const void* z,
+                      const void* g, void* grad_x, void* grad_lambda, int32_t* info, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+  int st = check_desc(desc);
+  if (st != WHS_OK) return st;
+  if (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31)) return WHS_ERR_UNSUPPORTED;
+  if (desc->n_series == 0) return WHS_OK;
+  if (!coef || !w || !lambda || !z || !g) return WHS_ERR_ARG;
+  const size_t e = elem(desc);
+  if (!aligned(coef, 8) || !aligned(z, e) || !aligned(g, e) || !aligned(grad_x, e) || !aligned(grad_lambda, e) ||
+      !aligned(lambda, e) || !aligned(info, 4))
+    return WHS_ERR_ARG;
+  if (!workspace || workspace_bytes < whs_workspace_bytes(desc) || !aligned(workspace, 8)) return WHS_ERR_WORKSPACE;
+  if (!grad_x && !grad_lambda && !info) return WHS_OK;
+  whs::LaunchDesc L = make_launch(desc);
+  L.coef = coef;
+  L.w = w;
+  L.lam = lambda;
+  L.rhs = g;
+  L.zin = z;
+  L.out = grad_x;
+  L.glam = grad_lambda;
+  L.info = info;
+  L.ws = static_cast<double*>(workspace);
+  return hip_status(whs::launch_backward(L, static_cast<hipStream_t>(stream)));
+}
+
 size_t whs_gcv_workspace_bytes(const whs_desc* desc) {
   if (check_desc(desc) != WHS_OK || desc->n_series == 0) return 0;
   return whs::gcv_checkpoint_bytes(desc->n_series, desc->interleave, desc->T, desc->d);

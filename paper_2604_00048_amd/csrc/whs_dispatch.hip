@@ -13,10 +13,19 @@ hipError_t run_backward_d1(const LaunchDesc&, hipStream_t);
 hipError_t run_backward_d2(const LaunchDesc&, hipStream_t);
 hipError_t run_backward_d3(const LaunchDesc&, hipStream_t);
 hipError_t run_backward_d4(const LaunchDesc&, hipStream_t);
+hipError_t run_solve_tab_d1(const LaunchDesc&, hipStream_t);
+hipError_t run_solve_tab_d2(const LaunchDesc&, hipStream_t);
+hipError_t run_solve_tab_d3(const LaunchDesc&, hipStream_t);
+hipError_t run_solve_tab_d4(const LaunchDesc&, hipStream_t);
+hipError_t run_backward_tab_d1(const LaunchDesc&, hipStream_t);
+hipError_t run_backward_tab_d2(const LaunchDesc&, hipStream_t);
+hipError_t run_backward_tab_d3(const LaunchDesc&, hipStream_t);
+hipError_t run_backward_tab_d4(const LaunchDesc&, hipStream_t);
 
 size_t checkpoint_bytes(int64_t P, int S, int T, int D, int C) {
   // the largest checkpoint area any call with this descriptor can use:
-  // the fast grouping and the generic one (given factor) are both covered
+  // the fast grouping, the generic one (given factor) and the uneven-time
+  // one are all covered
   const int64_t nb = (P + S - 1) / S;
   size_t mx = 0;
   for (int fast = 0; fast < 2; ++fast) {
@@ -34,10 +43,33 @@ size_t checkpoint_bytes(int64_t P, int S, int T, int D, int C) {
       rem -= g;
     }
   }
+  // the uneven-time grouping (fast path only)
+  for (int rem = C; rem > 0;) {
+    const int g = next_group_tab(rem);
+    size_t b = 0;
+    switch (D) {
+      case 1: b = ck_bytes_tab_d<1>(nb, S, T, g); break;
+      case 2: b = ck_bytes_tab_d<2>(nb, S, T, g); break;
+      case 3: b = ck_bytes_tab_d<3>(nb, S, T, g); break;
+      case 4: b = ck_bytes_tab_d<4>(nb, S, T, g); break;
+      default: return 0;
+    }
+    if (b > mx) mx = b;
+    rem -= g;
+  }
   return mx;
 }
 
 hipError_t launch_solve(const LaunchDesc& L, hipStream_t stream) {
+  if (L.coef) {
+    switch (L.D) {
+      case 1: return run_solve_tab_d1(L, stream);
+      case 2: return run_solve_tab_d2(L, stream);
+      case 3: return run_solve_tab_d3(L, stream);
+      case 4: return run_solve_tab_d4(L, stream);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (L.D) {
     case 1: return run_solve_d1(L, stream);
     case 2: return run_solve_d2(L, stream);
@@ -48,6 +80,15 @@ hipError_t launch_solve(const LaunchDesc& L, hipStream_t stream) {
 }
 
 hipError_t launch_backward(const LaunchDesc& L, hipStream_t stream) {
+  if (L.coef) {
+    switch (L.D) {
+      case 1: return run_backward_tab_d1(L, stream);
+      case 2: return run_backward_tab_d2(L, stream);
+      case 3: return run_backward_tab_d3(L, stream);
+      case 4: return run_backward_tab_d4(L, stream);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (L.D) {
     case 1: return run_backward_d1(L, stream);
     case 2: return run_backward_d2(L, stream);

@@ -58,11 +58,12 @@ struct FastArgs {
   void* glam;
   int32_t* info;
   double* ck;
+  const double* coef;  // rows of D on uneven times, (T-D) x (D+1); null on the daily grid
   int write_info;
   int glam_accum;
 };
 
-template <int D, int C, int B, typename TS, bool BWD, bool PERDIFF>
+template <int D, int C, int B, typename TS, bool BWD, bool PERDIFF, bool TAB = false>
 struct Fast {
   static constexpr int NF = ck_fields<D, C>();
   static constexpr uint32_t ES = sizeof(TS);
@@ -82,12 +83,21 @@ struct Fast {
   TS* ob;
   TS* gb;
   double* ckb;
+  const double* ctab;  // coefficient table (TAB only); the same for every series
   int T, S, Ctot, c0, nt;
   uint32_t Rx;  // bytes per row of x / z / g
   // per lane
   uint32_t lx, lw, lc;
   double lam_scalar;
   bool accum;
+
+  // row k of D's coefficient table (wave-uniform); zero outside 0..T-D-1
+  __device__ __forceinline__ void crow(int k, double (&c)[D + 1]) const {
+    const bool in = k >= 0 && k < T - D;
+    const double* r = ctab + (int64_t)(in ? k : 0) * (D + 1);
+#pragma unroll
+    for (int j = 0; j <= D; ++j) c[j] = in ? r[j] : 0.0;
+  }
 
   // rows of a tile starting at t0 that lie inside [0, lim); 0 for tiles outside
   __device__ __forceinline__ int rows_from(int t0, int lim) const {
@@ -140,7 +150,23 @@ struct Fast {
 #pragma unroll
     for (int m = 1; m <= D; ++m) lwv[m] = st.lw[m];
     double om[D + 1];
-    omega_row<D>(lwv, obs ? 1.0 : 0.0, om);
+    if constexpr (TAB) {
+      double cwv[D + 1][D + 1];
+      crow(t, cwv[0]);
+#pragma unroll
+      for (int m = 1; m <= D; ++m)
+#pragma unroll
+        for (int j = 0; j <= D; ++j) cwv[m][j] = st.cw[m][j];
+      omega_row_tab<D>(lwv, cwv, obs ? 1.0 : 0.0, om);
+#pragma unroll
+      for (int m = D; m >= 2; --m)
+#pragma unroll
+        for (int j = 0; j <= D; ++j) st.cw[m][j] = st.cw[m - 1][j];
+#pragma unroll
+      for (int j = 0; j <= D; ++j) st.cw[1][j] = cwv[0][j];
+    } else {
+      omega_row<D>(lwv, obs ? 1.0 : 0.0, om);
+    }
     ldl_step<D, C>(st, om, l, dt, invdt);
 #pragma unroll
     for (int m = D; m >= 2; --m) st.lw[m] = st.lw[m - 1];
@@ -238,6 +264,10 @@ struct Fast {
                                            double& gsum) const {
     State<D, C> st;
     restore(st, ckv, lwin);
+    if constexpr (TAB) {
+#pragma unroll
+      for (int m = 1; m <= D; ++m) crow(t0 - m, st.cw[m]);
+    }
     double lt[B][D + 1];
     double yd[B][C];
 #pragma unroll
@@ -288,15 +318,22 @@ struct Fast {
         double zin[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) zin[c] = to_f64(tl.z[s][c]);
+        double crw[D + 1];  // coefficients of row t of D
+        if constexpr (TAB) {
+          crow(t, crw);
+        } else {
+#pragma unroll
+          for (int i = 0; i <= D; ++i) crw[i] = cdiff<D>(i);
+        }
         double gt = 0.0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          double du = cdiff<D>(0) * zt[c];
-          double dz = cdiff<D>(0) * zin[c];
+          double du = crw[0] * zt[c];
+          double dz = crw[0] * zin[c];
 #pragma unroll
           for (int i = 1; i <= D; ++i) {
-            du = __builtin_fma(cdiff<D>(i), zn[i][c], du);
-            dz = __builtin_fma(cdiff<D>(i), xn[i][c], dz);
+            du = __builtin_fma(crw[i], zn[i][c], du);
+            dz = __builtin_fma(crw[i], xn[i][c], dz);
           }
           gt = __builtin_fma(-du, dz, gt);
         }
@@ -346,7 +383,18 @@ struct Fast {
       lwv[0] = ltv;
       for (int m = 1; m <= D; ++m) lwv[m] = st.lw[m];
       double om[D + 1], l[D + 1], dt, invdt;
-      omega_row<D>(lwv, obs ? 1.0 : 0.0, om);
+      if constexpr (TAB) {
+        double cwv[D + 1][D + 1];
+        crow(t, cwv[0]);
+        for (int m = 1; m <= D; ++m)
+          for (int j = 0; j <= D; ++j) cwv[m][j] = st.cw[m][j];
+        omega_row_tab<D>(lwv, cwv, obs ? 1.0 : 0.0, om);
+        for (int m = D; m >= 2; --m)
+          for (int j = 0; j <= D; ++j) st.cw[m][j] = st.cw[m - 1][j];
+        for (int j = 0; j <= D; ++j) st.cw[1][j] = cwv[0][j];
+      } else {
+        omega_row<D>(lwv, obs ? 1.0 : 0.0, om);
+      }
       ldl_step<D, C>(st, om, l, dt, invdt);
       for (int m = D; m >= 2; --m) st.lw[m] = st.lw[m - 1];
       st.lw[1] = ltv;
@@ -371,6 +419,7 @@ struct Fast {
     zb = BWD ? static_cast<const TS*>(a.zin) + bidx * T * Ctot * S : nullptr;
     ob = a.out ? static_cast<TS*>(a.out) + bidx * T * Ctot * S : nullptr;
     gb = (BWD && a.glam && PERDIFF) ? static_cast<TS*>(a.glam) + bidx * (T - D) * S : nullptr;
+    ctab = a.coef;
     accum = a.glam_accum != 0;
     const bool live = p < a.P;
     // padding slots of the last block: an offset beyond every buffer range
@@ -456,9 +505,9 @@ struct Fast {
   }
 };
 
-template <int D, int C, int B, typename TS, bool BWD, bool PERDIFF>
+template <int D, int C, int B, typename TS, bool BWD, bool PERDIFF, bool TAB>
 __global__ __launch_bounds__(256) void k_fast(FastArgs a) {
-  Fast<D, C, B, TS, BWD, PERDIFF> k;
+  Fast<D, C, B, TS, BWD, PERDIFF, TAB> k;
   k.run(a);
 }
 

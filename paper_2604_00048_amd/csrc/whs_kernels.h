@@ -21,12 +21,15 @@ struct LaunchDesc {
   void* glam;         // grad_lambda (backward)
   int32_t* info;
   double* ws;         // checkpoint workspace
+  const double* coef = nullptr;  // rows of D on uneven sample times, (T-D) x (D+1); null: daily grid
 };
 
 size_t checkpoint_bytes(int64_t P, int S, int T, int D, int C);
 hipError_t launch_solve(const LaunchDesc& L, hipStream_t stream);
 hipError_t launch_backward(const LaunchDesc& L, hipStream_t stream);
 hipError_t launch_factor(const LaunchDesc& L, hipStream_t stream);
+// coefficient table of D from sample times: coef[k][j] = d! / prod_{m != j} (t[k+j] - t[k+m])
+hipError_t launch_diff_coef(const double* times, int T, int D, double* coef, hipStream_t stream);
 
 }  // namespace whs
 

@@ -47,6 +47,7 @@ template <> __device__ __forceinline__ double from_f64<double>(double v) { retur
 //   R[j][k]  = L[t-j, t-j-k]               (j = 1..D-1, k = 1..D-j)
 //   y[j][c]  = y[t-j][c]                   (j = 1..D)
 //   lw[m]    = lambda_{t-m}                (m = 1..D; per-difference weights)
+//   cw[m][j] = c_{t-m, j}                  (m = 1..D; rows of D on uneven times)
 // Index 0 entries are unused.  A zero state is the state before t = 0: rows
 // with negative index contribute nothing because Omega has no entries there.
 template <int D, int C>
@@ -55,12 +56,15 @@ struct State {
   double R[D + 1][D + 1];
   double y[D + 1][C];
   double lw[D + 1];
+  double cw[D + 1][D + 1];
 
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int j = 0; j <= D; ++j) {
       invD[j] = 0.0;
       lw[j] = 0.0;
+#pragma unroll
+      for (int k = 0; k <= D; ++k) cw[j][k] = 0.0;
 #pragma unroll
       for (int k = 0; k <= D; ++k) R[j][k] = 0.0;
 #pragma unroll
@@ -117,6 +121,22 @@ __device__ __forceinline__ void omega_row(const double (&lw)[D + 1], double wt, 
     double a = 0.0;
 #pragma unroll
     for (int m = i; m <= D; ++m) a = __builtin_fma(lw[m], cdiff<D>(m) * cdiff<D>(m - i), a);
+    om[i] = a;
+  }
+  om[0] += wt;
+}
+
+// The same row when D has its own coefficients per row (uneven sample times,
+// Sec. II): with cw[m][j] = c_{t-m, j} (row t-m of D),
+// om[i] = [i = 0] w_t + sum_{m=i..D} lw[m] c_{t-m, m} c_{t-m, m-i}.
+template <int D>
+__device__ __forceinline__ void omega_row_tab(const double (&lw)[D + 1], const double (&cw)[D + 1][D + 1], double wt,
+                                              double (&om)[D + 1]) {
+#pragma unroll
+  for (int i = 0; i <= D; ++i) {
+    double a = 0.0;
+#pragma unroll
+    for (int m = i; m <= D; ++m) a = __builtin_fma(lw[m] * cw[m][m], cw[m][m - i], a);
     om[i] = a;
   }
   om[0] += wt;

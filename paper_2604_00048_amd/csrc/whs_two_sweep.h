@@ -415,14 +415,17 @@ __global__ __launch_bounds__(256) void k_two_sweep(Args a) {
 // host-side launchers
 // ---------------------------------------------------------------------------
 
-template <int D, int C>
+// Steps per tile.  The uneven-time kernels also carry a window of D's rows,
+// so they use shallower tiles to stay clear of register spills.
+template <int D, int C, bool TAB = false>
 constexpr int tile_depth() {
+  if (TAB) return C == 1 ? 16 : 8;
   return C == 1 ? 24 : (C == 2 ? 16 : 8);
 }
 
-template <int D, int C, typename TS, Src SRC, Mode MODE, bool PERDIFF>
+template <int D, int C, typename TS, Src SRC, Mode MODE, bool PERDIFF, bool TAB = false>
 hipError_t launch_fast(const LaunchDesc& L, int c0, int write_info, hipStream_t stream) {
-  constexpr int B = tile_depth<D, C>();
+  constexpr int B = tile_depth<D, C, TAB>();
   FastArgs f;
   f.P = L.P;
   f.T = L.T;
@@ -438,12 +441,13 @@ hipError_t launch_fast(const LaunchDesc& L, int c0, int write_info, hipStream_t 
   f.glam = L.glam;
   f.info = L.info;
   f.ck = L.ws;
+  f.coef = L.coef;
   f.write_info = write_info;
   f.glam_accum = c0 > 0;
   const int threads = 256;
   const int64_t blocks = (L.P + threads - 1) / threads;
-  hipLaunchKernelGGL((k_fast<D, C, B, TS, MODE == Mode::Backward, PERDIFF>), dim3((unsigned)blocks), dim3(threads),
-                     0, stream, f);
+  hipLaunchKernelGGL((k_fast<D, C, B, TS, MODE == Mode::Backward, PERDIFF, TAB>), dim3((unsigned)blocks),
+                     dim3(threads), 0, stream, f);
   return hipGetLastError();
 }
 
@@ -475,9 +479,9 @@ hipError_t launch_generic(const LaunchDesc& L, int c0, int write_info, hipStream
   return hipGetLastError();
 }
 
-template <int D, int C>
+template <int D, int C, bool TAB = false>
 size_t ck_bytes_for(int64_t nb, int S, int T) {
-  constexpr int B = tile_depth<D, C>();
+  constexpr int B = tile_depth<D, C, TAB>();
   const int64_t nt = (T + B - 1) / B;
   return (size_t)nb * nt * ck_fields<D, C>() * S * sizeof(double);
 }
@@ -494,6 +498,14 @@ inline int next_group(int remaining, bool fast) {
       if (g <= remaining) return g;
   }
   return remaining >= 2 ? 2 : 1;
+}
+
+// band groups of the uneven-time kernels
+inline int next_group_tab(int remaining) { return remaining >= 4 ? 4 : 1; }
+
+template <int D>
+inline size_t ck_bytes_tab_d(int64_t nb, int S, int T, int g) {
+  return g == 4 ? ck_bytes_for<D, 4, true>(nb, S, T) : ck_bytes_for<D, 1, true>(nb, S, T);
 }
 
 template <int D>
@@ -533,6 +545,29 @@ hipError_t run_groups(const LaunchDesc& L, hipStream_t stream) {
     c0 += g;
   }
   return hipSuccess;
+}
+
+// Uneven sample times (a coefficient table for D): fast path only, built for
+// 4 and 1 bands per launch.
+template <int D, typename TS, Mode MODE, bool PERDIFF>
+hipError_t run_groups_tab(const LaunchDesc& L, hipStream_t stream) {
+  int c0 = 0;
+  while (c0 < L.C) {
+    const int g = next_group_tab(L.C - c0);
+    const int wi = c0 == 0;
+    const hipError_t e = g == 4 ? launch_fast<D, 4, TS, Src::Fused, MODE, PERDIFF, true>(L, c0, wi, stream)
+                                : launch_fast<D, 1, TS, Src::Fused, MODE, PERDIFF, true>(L, c0, wi, stream);
+    if (e != hipSuccess) return e;
+    c0 += g;
+  }
+  return hipSuccess;
+}
+
+template <int D, Mode MODE>
+hipError_t run_mode_tab_d(const LaunchDesc& L, hipStream_t stream) {
+  if (L.f64) return L.perdiff ? run_groups_tab<D, double, MODE, true>(L, stream)
+                              : run_groups_tab<D, double, MODE, false>(L, stream);
+  return L.perdiff ? run_groups_tab<D, float, MODE, true>(L, stream) : run_groups_tab<D, float, MODE, false>(L, stream);
 }
 
 // All storage types and weight kinds of one order and mode.

@@ -69,6 +69,9 @@ SIGNATURES = {
     "whs_backward": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "whs_gcv_workspace_bytes": (_SZ, [_DP]),
     "whs_gcv": (ctypes.c_int, [_DP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "whs_diff_coef": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP]),
+    "whs_solve_coef": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "whs_backward_coef": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "whs_variance_workspace_bytes": (_SZ, [_DP]),
     "whs_variance": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "whs_plan_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(WhsGroup), ctypes.c_int32,
@@ -192,10 +195,32 @@ def whs_factor(w: torch.Tensor, lam: torch.Tensor, d: int, P: int | None = None,
     return factor, info
 
 
+def whs_diff_coef(times: torch.Tensor, d: int, coef=None) -> torch.Tensor:
+    """Rows of the order-``d`` difference operator on the sample times ``times``
+    (1-D float64 device tensor, strictly increasing): ``(T-d, d+1)`` float64."""
+    _need_gpu(times, coef)
+    if times.dtype != torch.float64 or times.dim() != 1 or not times.is_contiguous():
+        raise TypeError("times must be a contiguous 1-D float64 device tensor")
+    T = times.numel()
+    if coef is None:
+        coef = torch.empty((max(T - d, 0), d + 1), dtype=torch.float64, device=times.device)
+    _check(lib().whs_diff_coef(_ptr(times), T, d, _ptr(coef), _stream(times.device)), "whs_diff_coef")
+    return coef
+
+
+def _check_coef(coef, T, d):
+    if coef.dtype != torch.float64 or tuple(coef.shape) != (T - d, d + 1) or not coef.is_contiguous():
+        raise ValueError(f"coef must be a contiguous float64 ({T - d}, {d + 1}) device tensor")
+
+
 def whs_solve(x: torch.Tensor, w: torch.Tensor, lam: torch.Tensor | None, d: int, P: int | None = None,
-              factor=None, z=None, info=None, workspace=None):
-    """``z = Omega^{-1} W x`` per series and band.  Returns ``(z, info)``."""
-    _need_gpu(x, w, lam, factor, z, info, workspace)
+              factor=None, z=None, info=None, workspace=None, coef=None):
+    """``z = Omega^{-1} W x`` per series and band.  Returns ``(z, info)``.
+
+    ``coef``: rows of ``D`` on uneven sample times (``whs_diff_coef``); the
+    daily grid when ``None``.
+    """
+    _need_gpu(x, w, lam, factor, z, info, workspace, coef)
     nb, T, C, S, P = _geometry(x, P)
     if tuple(w.shape) != (nb, T, S) or w.dtype != torch.uint8:
         raise ValueError(f"w must be uint8 of shape {(nb, T, S)}")
@@ -208,6 +233,14 @@ def whs_solve(x: torch.Tensor, w: torch.Tensor, lam: torch.Tensor | None, d: int
     if info is None:
         info = torch.empty(P, dtype=torch.int32, device=x.device)
     ws, n = _workspace(desc, x.device, workspace)
+    if coef is not None:
+        if factor is not None:
+            raise ValueError("uneven sample times use the fused path (no factor)")
+        _check_coef(coef, T, d)
+        _check(lib().whs_solve_coef(ctypes.byref(desc), _ptr(coef), _ptr(w), _ptr(lam), _ptr(x), _ptr(z),
+                                    _ptr(info), _ptr(ws), ws.numel() * ws.element_size(), _stream(x.device)),
+               "whs_solve_coef")
+        return z, info
     _check(lib().whs_solve(ctypes.byref(desc), _ptr(w), _ptr(lam), _ptr(factor), _ptr(x), _ptr(z), _ptr(info),
                            _ptr(ws), ws.numel() * ws.element_size(), _stream(x.device)), "whs_solve")
     return z, info
@@ -215,12 +248,13 @@ def whs_solve(x: torch.Tensor, w: torch.Tensor, lam: torch.Tensor | None, d: int
 
 def whs_backward(w: torch.Tensor, lam: torch.Tensor | None, z: torch.Tensor, g: torch.Tensor, d: int,
                  P: int | None = None, factor=None, need_x: bool = True, need_lambda: bool = True,
-                 grad_x=None, grad_lambda=None, info=None, workspace=None, lambda_kind: int | None = None):
+                 grad_x=None, grad_lambda=None, info=None, workspace=None, lambda_kind: int | None = None,
+                 coef=None):
     """Adjoint against ``g``: ``grad_x = W Omega^{-1} g``, ``grad_lambda_k = -(D u)_k (D z)_k``.
 
-    Returns ``(grad_x or None, grad_lambda or None, info)``.
+    Returns ``(grad_x or None, grad_lambda or None, info)``.  ``coef`` as in ``whs_solve``.
     """
-    _need_gpu(w, lam, z, g, factor, grad_x, grad_lambda, info, workspace)
+    _need_gpu(w, lam, z, g, factor, grad_x, grad_lambda, info, workspace, coef)
     nb, T, C, S, P = _geometry(z, P)
     if tuple(g.shape) != tuple(z.shape) or g.dtype != z.dtype:
         raise ValueError("g must match z in shape and dtype")
@@ -234,6 +268,15 @@ def whs_backward(w: torch.Tensor, lam: torch.Tensor | None, z: torch.Tensor, g: 
     if info is None:
         info = torch.empty(P, dtype=torch.int32, device=z.device)
     ws, n = _workspace(desc, z.device, workspace)
+    if coef is not None:
+        if factor is not None:
+            raise ValueError("uneven sample times use the fused path (no factor)")
+        _check_coef(coef, T, d)
+        _check(lib().whs_backward_coef(ctypes.byref(desc), _ptr(coef), _ptr(w), _ptr(lam), _ptr(z), _ptr(g),
+                                       _ptr(grad_x if need_x else None), _ptr(grad_lambda if need_lambda else None),
+                                       _ptr(info), _ptr(ws), ws.numel() * ws.element_size(), _stream(z.device)),
+               "whs_backward_coef")
+        return (grad_x if need_x else None), (grad_lambda if need_lambda else None), info
     _check(lib().whs_backward(ctypes.byref(desc), _ptr(w), _ptr(lam), _ptr(factor), _ptr(z), _ptr(g),
                               _ptr(grad_x if need_x else None), _ptr(grad_lambda if need_lambda else None),
                               _ptr(info), _ptr(ws), ws.numel() * ws.element_size(), _stream(z.device)),

@@ -47,11 +47,11 @@ def from_device_rows(lt, P):
     return synth.unpack_rows(lt.cpu(), P).double().numpy()
 
 
-def lapack_spread(x, w, lam, d, zref):
+def lapack_spread(x, w, lam, d, zref, coef=None):
     """Norm-wise distance between the oracle and LAPACK's banded solver per series
     (how far two correct FP64 solvers already differ on this input)."""
     import scipy.linalg
-    AB = R.omega_band(w, lam, d)
+    AB = R.omega_band(w, lam, d, coef)
     out = np.zeros(x.shape[0])
     for p in range(x.shape[0]):
         ref = scipy.linalg.solveh_banded(AB[p], np.where(w[p][:, None] != 0, x[p], 0.0), lower=True)
@@ -59,7 +59,7 @@ def lapack_spread(x, w, lam, d, zref):
     return out
 
 
-def assert_solution(z, zref, x, w, lam, d, f64: bool, info=None):
+def assert_solution(z, zref, x, w, lam, d, f64: bool, info=None, coef=None):
     """FP64: per-series error <= max(1e-10, 10 x LAPACK spread); FP32 storage:
     <= 1e-4.  Always: componentwise backward error <= 1e-13 (FP64) / 1e-6 (FP32)."""
     ok = np.ones(z.shape[0], bool) if info is None else (info == 0)
@@ -67,12 +67,12 @@ def assert_solution(z, zref, x, w, lam, d, f64: bool, info=None):
     if f64:
         bad = err > 1e-10
         if bad.any():
-            spread = lapack_spread(x[ok][bad], w[ok][bad], np.asarray(lam)[ok][bad], d, zref[ok][bad])
+            spread = lapack_spread(x[ok][bad], w[ok][bad], np.asarray(lam)[ok][bad], d, zref[ok][bad], coef)
             assert (err[bad] <= 10 * spread).all(), (err[bad].max(), spread.max())
-        be = R.backward_error(x[ok], w[ok], np.asarray(lam)[ok], d, z[ok])
+        be = R.backward_error(x[ok], w[ok], np.asarray(lam)[ok], d, z[ok], coef)
         assert be.max() <= 1e-13, be.max()
     else:
         assert err.max() <= 1e-4, err.max()
-        be = R.backward_error(x[ok], w[ok], np.asarray(lam)[ok], d, z[ok])
+        be = R.backward_error(x[ok], w[ok], np.asarray(lam)[ok], d, z[ok], coef)
         assert be.max() <= 1e-6, be.max()
     return err

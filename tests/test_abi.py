@@ -94,9 +94,10 @@ def test_empty_batch_is_a_noop():
 
 
 def test_workspace_and_factor_sizes():
-    # order 2, one band: 2 + 1 + 2 = 5 doubles per tile of 24 steps per series
+    # order 2, one band: 2 + 1 + 2 = 5 doubles per tile per series; the largest
+    # user is the uneven-time kernel with tiles of 16 steps
     desc = whs.make_desc(100, 365, 2, 1, 64, 0, 1)
-    tiles = (365 + 23) // 24
+    tiles = (365 + 15) // 16
     assert whs.workspace_bytes(desc) == 2 * tiles * 5 * 64 * 8
     assert whs.lib().whs_factor_bytes(ctypes.byref(desc)) == 128 * 3 * 365 * 8
 
@@ -162,3 +163,21 @@ def test_variance_validation():
     assert L.whs_variance_workspace_bytes(ctypes.byref(desc)) == ((50 + 15) // 16) * 5 * 64 * 8
     empty = whs.make_desc(0, 50, 2, 1, 64, 0, 1)
     assert L.whs_variance(ctypes.byref(empty), None, None, None, None, None, 0, None) == 0
+
+
+def test_uneven_time_validation():
+    L = whs.lib()
+    assert L.whs_diff_coef(FAKE, 10, 0, FAKE, None) == -1
+    assert L.whs_diff_coef(FAKE, 2, 2, FAKE, None) == -1          # T <= d
+    assert L.whs_diff_coef(FAKE, 10, 5, FAKE, None) == -2
+    assert L.whs_diff_coef(None, 10, 2, FAKE, None) == -1
+    assert L.whs_diff_coef(FAKE, 10, 2, FAKE_ODD, None) == -1
+    desc = whs.make_desc(10, 50, 2, 1, 32, 0, 1)        # interleave not a multiple of 64
+    assert L.whs_solve_coef(ctypes.byref(desc), FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, 1 << 30, None) == -2
+    desc = whs.make_desc(10, 50, 2, 1, 64, 0, 1)
+    assert L.whs_solve_coef(ctypes.byref(desc), None, FAKE, FAKE, FAKE, FAKE, None, FAKE, 1 << 30, None) == -1
+    assert L.whs_solve_coef(ctypes.byref(desc), FAKE, FAKE, FAKE, FAKE, FAKE, None, None, 0, None) == -4
+    assert L.whs_backward_coef(ctypes.byref(desc), FAKE, FAKE, FAKE, FAKE, FAKE_ODD, None, None, None, FAKE,
+                               1 << 30, None) == -1
+    empty = whs.make_desc(0, 50, 2, 1, 64, 0, 1)
+    assert L.whs_solve_coef(ctypes.byref(empty), None, None, None, None, None, None, None, 0, None) == 0
