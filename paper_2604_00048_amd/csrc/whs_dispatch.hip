@@ -24,13 +24,13 @@ hipError_t run_backward_tab_d4(const LaunchDesc&, hipStream_t);
 
 size_t checkpoint_bytes(int64_t P, int S, int T, int D, int C) {
   // the largest checkpoint area any call with this descriptor can use:
-  // the fast grouping, the generic one (given factor) and the uneven-time
-  // one are all covered
+  // the fast groupings (solve and adjoint), the generic one (given factor)
+  // and the uneven-time one are all covered
   const int64_t nb = (P + S - 1) / S;
   size_t mx = 0;
-  for (int fast = 0; fast < 2; ++fast) {
+  for (int variant = 0; variant < 3; ++variant) {  // generic, fast solve, fast backward
     for (int rem = C; rem > 0;) {
-      const int g = next_group(rem, fast != 0);
+      const int g = next_group(rem, variant > 0, D, variant == 2);
       size_t b = 0;
       switch (D) {
         case 1: b = ck_bytes_d<1>(nb, S, T, g); break;

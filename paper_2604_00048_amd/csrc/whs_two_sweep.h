@@ -420,7 +420,7 @@ __global__ __launch_bounds__(256) void k_two_sweep(Args a) {
 template <int D, int C, bool TAB = false>
 constexpr int tile_depth() {
   if (TAB) return C == 1 ? 16 : 8;
-  return C == 1 ? 24 : (C == 2 ? 16 : 8);
+  return C == 1 ? 24 : 8;
 }
 
 template <int D, int C, typename TS, Src SRC, Mode MODE, bool PERDIFF, bool TAB = false>
@@ -486,18 +486,33 @@ size_t ck_bytes_for(int64_t nb, int S, int T) {
   return (size_t)nb * nt * ck_fields<D, C>() * S * sizeof(double);
 }
 
-// RHS group sizes: the fast path (interleave a multiple of 64, weights and
-// mask given) is built for 10, 4, 2 and 1 bands per launch; the generic path
-// (any interleave, or a given factor) for 2 and 1.  A call covers C bands by
-// greedy groups; every group recomputes the same factor.
+// RHS group sizes.  A call covers C bands by greedy groups, each one launch
+// that recomputes the same factor.  The largest group is the largest one whose
+// kernel compiles without register spills: 5 bands for the solve of order
+// d <= 2, 3 bands otherwise (fast path: interleave a multiple of 64, weights
+// and mask given); the generic path (any interleave, or a given factor) uses
+// 2 and 1.
 inline bool fast_path(const LaunchDesc& L) { return !L.fac && L.S % 64 == 0 && L.P < ((int64_t)1 << 31); }
 
-inline int next_group(int remaining, bool fast) {
+inline int max_group(int D, bool bwd) { return (!bwd && D <= 2) ? 5 : 3; }
+
+inline int next_group(int remaining, bool fast, int D, bool bwd) {
   if (fast) {
-    for (int g : {10, 4, 2, 1})
-      if (g <= remaining) return g;
+    const int g = max_group(D, bwd);
+    return remaining < g ? remaining : g;
   }
   return remaining >= 2 ? 2 : 1;
+}
+
+template <int D>
+inline size_t ck_bytes_d(int64_t nb, int S, int T, int g) {
+  switch (g) {
+    case 5: return ck_bytes_for<D, 5>(nb, S, T);
+    case 4: return ck_bytes_for<D, 4>(nb, S, T);
+    case 3: return ck_bytes_for<D, 3>(nb, S, T);
+    case 2: return ck_bytes_for<D, 2>(nb, S, T);
+    default: return ck_bytes_for<D, 1>(nb, S, T);
+  }
 }
 
 // band groups of the uneven-time kernels
@@ -508,29 +523,28 @@ inline size_t ck_bytes_tab_d(int64_t nb, int S, int T, int g) {
   return g == 4 ? ck_bytes_for<D, 4, true>(nb, S, T) : ck_bytes_for<D, 1, true>(nb, S, T);
 }
 
-template <int D>
-inline size_t ck_bytes_d(int64_t nb, int S, int T, int g) {
-  switch (g) {
-    case 10: return ck_bytes_for<D, 10>(nb, S, T);
-    case 4: return ck_bytes_for<D, 4>(nb, S, T);
-    case 2: return ck_bytes_for<D, 2>(nb, S, T);
-    default: return ck_bytes_for<D, 1>(nb, S, T);
-  }
-}
-
 template <int D, typename TS, Src SRC, Mode MODE, bool PERDIFF>
 hipError_t run_groups(const LaunchDesc& L, hipStream_t stream) {
   const bool fast = SRC == Src::Fused && fast_path(L);
+  constexpr bool kBwd = MODE == Mode::Backward;
   int c0 = 0;
   while (c0 < L.C) {
-    const int g = next_group(L.C - c0, fast);
+    const int g = next_group(L.C - c0, fast, D, kBwd);
     const int wi = c0 == 0;  // the first group writes info; later groups add to grad_lambda
     hipError_t e;
     if constexpr (SRC == Src::Fused) {
       if (fast) {
         switch (g) {
-          case 10: e = launch_fast<D, 10, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
-          case 4: e = launch_fast<D, 4, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
+          case 5:
+          case 4:
+            if constexpr (!kBwd && D <= 2) {
+              e = g == 5 ? launch_fast<D, 5, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream)
+                         : launch_fast<D, 4, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream);
+            } else {
+              e = hipErrorInvalidValue;  // never chosen for this order and mode
+            }
+            break;
+          case 3: e = launch_fast<D, 3, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
           case 2: e = launch_fast<D, 2, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
           default: e = launch_fast<D, 1, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
         }
