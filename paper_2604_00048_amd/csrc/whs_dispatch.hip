@@ -61,6 +61,7 @@ size_t checkpoint_bytes(int64_t P, int S, int T, int D, int C) {
 }
 
 hipError_t launch_solve(const LaunchDesc& L, hipStream_t stream) {
+  if (chunk_path(L)) return launch_chunk(L, false, stream);
   if (L.coef) {
     switch (L.D) {
       case 1: return run_solve_tab_d1(L, stream);
@@ -80,6 +81,7 @@ hipError_t launch_solve(const LaunchDesc& L, hipStream_t stream) {
 }
 
 hipError_t launch_backward(const LaunchDesc& L, hipStream_t stream) {
+  if (chunk_path(L)) return launch_chunk(L, true, stream);
   if (L.coef) {
     switch (L.D) {
       case 1: return run_backward_tab_d1(L, stream);

@@ -60,3 +60,11 @@ size_t var_checkpoint_bytes(int64_t P, int S, int T, int D);
 hipError_t launch_var(const LaunchDesc& L, hipStream_t stream);
 
 }  // namespace whs
+
+namespace whs {
+
+// several lanes per series (interleave 1, one band, order <= 2): see whs_chunk.hip
+bool chunk_path(const LaunchDesc& L);
+hipError_t launch_chunk(const LaunchDesc& L, bool bwd, hipStream_t stream);
+
+}  // namespace whs

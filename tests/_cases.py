@@ -59,6 +59,20 @@ def lapack_spread(x, w, lam, d, zref, coef=None):
     return out
 
 
+def adjoint_spread(g, w, lam, d, coef=None):
+    """Norm-wise distance per series between the oracle's u = Omega^{-1} g and
+    LAPACK's banded solve of the same system."""
+    import scipy.linalg
+    g3 = g if g.ndim == 3 else g[:, :, None]
+    u, _ = R.solve_band_rhs(g3, w, lam, d, coef)
+    AB = R.omega_band(w, lam, d, coef)
+    out = np.zeros(g3.shape[0])
+    for p in range(g3.shape[0]):
+        ref = scipy.linalg.solveh_banded(AB[p], g3[p], lower=True)
+        out[p] = np.abs(ref - u[p]).max() / max(np.abs(ref).max(), 1e-300)
+    return out
+
+
 EPS = float(np.finfo(np.float64).eps)
 
 
