@@ -36,15 +36,18 @@ def alg_bytes(T: int, d: int, C: int, esz: int, per_diff: bool):
     return fwd, bwd
 
 
+# Sources of the two-sweep kernels whose HBM counters profiles/traffic.json holds.
+TRAFFIC_SOURCES = ("whs_step.h", "whs_fast.h", "whs_two_sweep.h", "whs_kernels.h", "whs_dispatch.hip",
+                   "inst_solve_d2.hip", "inst_backward_d2.hip")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2604_00048_amd", "csrc")
-    for dirpath, _, files in sorted(os.walk(csrc)):
-        for f in sorted(files):
-            if f.endswith((".hip", ".h")):
-                with open(os.path.join(dirpath, f), "rb") as fh:
-                    h.update(f.encode())
-                    h.update(fh.read())
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
