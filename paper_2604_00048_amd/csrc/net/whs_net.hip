@@ -39,13 +39,15 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __builtin_bit_cast(fl
 // MODE 0: + bias, ReLU, bfloat16 out (P,T,NOUT)
 // MODE 1: + bias, FP32 out of channel 0 only (P,T)            (last layer)
 // MODE 2: no bias, out *= (mask > 0), bfloat16 out (P,T,NOUT) (input gradient)
-// One workgroup = 64 time rows of one series; wave w computes output
-// channels 16w..16w+15 for all 64 rows (4 accumulator tiles).
+// A tile is 64 time rows of one series; wave w computes output channels
+// 16w..16w+15 for all 64 rows (4 accumulator tiles).  Each workgroup loads
+// its weights into registers once and then walks tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ... (the grid is bounded by the launcher).
 // ---------------------------------------------------------------------------
 template <int CIN, int NOUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wt,
                                               const float* __restrict__ bias, const uint16_t* __restrict__ mask,
-                                              void* __restrict__ out, int T, int ntiles) {
+                                              void* __restrict__ out, int T, int ntiles, int64_t total) {
   constexpr int KTOT = KT * CIN;
   constexpr int NS = (KTOT + 31) / 32;      // K steps of 32
   constexpr int ROWS = TM + 2 * HALO;       // input window rows
@@ -57,9 +59,6 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
   const int wave = threadIdx.x >> 6;
   const int g = lane >> 4;   // K group of this lane
   const int r16 = lane & 15;
-  const int64_t p = blockIdx.x / ntiles;
-  const int t0 = (int)(blockIdx.x - p * ntiles) * TM;
-  const uint16_t* inp = in + p * (int64_t)T * CIN;
 
   // weights of this wave's 16 output channels, all K steps, in registers
   bf16x8 wb[NS];
@@ -72,6 +71,13 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
     if (tap < KT) v = *reinterpret_cast<const u32x4*>(wt + ((int64_t)n * KT + tap) * CIN + c);
     wb[s] = __builtin_bit_cast(bf16x8, v);
   }
+  const float bv = (MODE != 2 && bias) ? bias[n] : 0.f;
+
+  for (int64_t tix = blockIdx.x; tix < total; tix += gridDim.x) {
+  const int64_t p = tix / ntiles;
+  const int t0 = (int)(tix - p * ntiles) * TM;
+  const uint16_t* inp = in + p * (int64_t)T * CIN;
+  __syncthreads();  // the previous tile's window and output tile are no longer read
   // input window rows t0-4 .. t0+67 (zero outside 0..T-1), 16-byte chunks
   constexpr int CH = CIN / 8;
   for (int i = threadIdx.x; i < ROWS * CH; i += blockDim.x) {
@@ -99,7 +105,6 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
   }
 
   // epilogue: lane holds rows 16m + 4g + j, column n
-  const float bv = (MODE != 2 && bias) ? bias[n] : 0.f;
   if constexpr (MODE == 1) {
     if (n == 0) {
       float* o = static_cast<float*>(out) + p * (int64_t)T;
@@ -111,7 +116,6 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
           if (t < T) o[t] = acc[m][j] + bv;
         }
     }
-    return;
   } else {
     constexpr int OS = NOUT + 8;
 #pragma unroll
@@ -144,32 +148,40 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
       *reinterpret_cast<u32x4*>(o + (int64_t)t * NOUT + 8 * c8) = v;
     }
   }
+  }  // tiles
 }
 
 // ---------------------------------------------------------------------------
 // Weight gradient: gW[n][tap][c] = sum_{p,t} gy[p,t,n] in[p,t+tap-4,c],
-// gb[n] = sum gy[p,t,n].  K = time: each step takes 32 time rows of one
-// series, gathers the transposed operands from LDS, and accumulates in
-// registers; workgroup w writes its partial sums to part[w] and
+// gb[n] = sum gy[p,t,n].  GEMM with K = time, done as
+//   gW[n][tap][c] = sum_u gy[u-tap+4][n] in[u][c]
+// so the input operand (columns c, 32 consecutive u) is the same for all
+// nine taps and the tap only shifts the gradient operand.  Each work item is
+// 32 time rows of one series, staged in LDS transposed (channel-major) so
+// every operand fragment is one aligned 16-byte read: the input fragments
+// directly, and each tap's gradient fragment is cut from a 16-element window
+// with funnel shifts.  Workgroup w writes partial sums to part[w];
 // k_wgrad_reduce adds them in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
 template <int CIN, int NOUT>
 __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ in, const uint16_t* __restrict__ gy,
                                                float* __restrict__ part, int64_t P, int T) {
-  constexpr int NN = KT * CIN;               // GEMM N
-  constexpr int NT = (NN + 15) / 16;         // N tiles of 16
-  constexpr int TK = 32;                     // time rows per step
-  constexpr int XR = TK + 2 * HALO;
-  constexpr int XS = CIN + 2;                // LDS strides in bf16 (odd words: fewer conflicts)
-  constexpr int GS = NOUT + 2;
-  __shared__ uint16_t xt[XR * XS];
-  __shared__ uint16_t gt[TK * GS];
+  constexpr int NN = KT * CIN;               // GEMM N (tap, c)
+  constexpr int CT = (CIN + 15) / 16;        // column tiles of 16 channels
+  constexpr int NT = KT * CT;                // accumulator tiles per wave
+  constexpr int TK = 32;                     // time rows per item
+  constexpr int GR = TK + 2 * HALO;          // gradient rows per item
+  constexpr int XS = TK + 8;                 // LDS row strides in bf16 (multiples of 8: aligned 16-byte reads)
+  constexpr int GS = GR + 8;
+  constexpr int XROWS = CT * 16;             // channel rows of xT (zero rows pad CIN = 8)
+  __shared__ __attribute__((aligned(16))) uint16_t xT[XROWS * XS];
+  __shared__ __attribute__((aligned(16))) uint16_t gT[NOUT * GS];
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int g = lane >> 4;
   const int r16 = lane & 15;
-  const int m = wave * 16 + r16;  // output channel of the A rows
+  const int m = wave * 16 + r16;  // output channel of this lane's A row
   const int64_t chunks = (T + TK - 1) / TK;
   const int64_t items = P * chunks;
 
@@ -177,6 +189,9 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ in, 
 #pragma unroll
   for (int q = 0; q < NT; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.f;
+  if (CIN < XROWS) {
+    for (int i = threadIdx.x; i < (XROWS - CIN) * XS; i += blockDim.x) xT[CIN * XS + i] = 0;
+  }
 
   for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
     const int64_t p = it / chunks;
@@ -184,48 +199,72 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ in, 
     const uint16_t* ip = in + p * (int64_t)T * CIN;
     const uint16_t* gp = gy + p * (int64_t)T * NOUT;
     __syncthreads();
-    for (int i = threadIdx.x; i < XR * CIN; i += blockDim.x) {
-      const int r = i / CIN, c = i % CIN;
-      const int t = t0 - HALO + r;
-      xt[r * XS + c] = (t >= 0 && t < T) ? ip[(int64_t)t * CIN + c] : (uint16_t)0;
+    // input rows t0 .. t0+31, 8 channels per 16-byte load, stored channel-major
+    for (int i = threadIdx.x; i < TK * (CIN / 8); i += blockDim.x) {
+      const int u = i / (CIN / 8), c0 = 8 * (i % (CIN / 8));
+      const int t = t0 + u;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (t < T) v = *reinterpret_cast<const u32x4*>(ip + (int64_t)t * CIN + c0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        xT[(c0 + 2 * q) * XS + u] = (uint16_t)(v[q] & 0xffffu);
+        xT[(c0 + 2 * q + 1) * XS + u] = (uint16_t)(v[q] >> 16);
+      }
     }
-    for (int i = threadIdx.x; i < TK * NOUT; i += blockDim.x) {
-      const int r = i / NOUT, c = i % NOUT;
-      const int t = t0 + r;
-      gt[r * GS + c] = (t < T) ? gp[(int64_t)t * NOUT + c] : (uint16_t)0;
+    // gradient rows t0-4 .. t0+35
+    for (int i = threadIdx.x; i < GR * (NOUT / 8); i += blockDim.x) {
+      const int r = i / (NOUT / 8), n0 = 8 * (i % (NOUT / 8));
+      const int t = t0 - HALO + r;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (t >= 0 && t < T) v = *reinterpret_cast<const u32x4*>(gp + (int64_t)t * NOUT + n0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        gT[(n0 + 2 * q) * GS + r] = (uint16_t)(v[q] & 0xffffu);
+        gT[(n0 + 2 * q + 1) * GS + r] = (uint16_t)(v[q] >> 16);
+      }
     }
     __syncthreads();
-    // A: gy^T rows m, K = time 8g .. 8g+7
-    bf16x8 a;
+    // gradient window of this lane: rows 8g .. 8g+15 of channel m (taps cut 8 of them)
+    const u32x4 w0 = *reinterpret_cast<const u32x4*>(gT + m * GS + 8 * g);
+    const u32x4 w1 = *reinterpret_cast<const u32x4*>(gT + m * GS + 8 * g + 8);
+    const uint32_t W[8] = {w0[0], w0[1], w0[2], w0[3], w1[0], w1[1], w1[2], w1[3]};
+    // input fragments: column c = 16 ct + r16, rows 8g .. 8g+7
+    bf16x8 bx[CT];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const uint16_t b = gt[(8 * g + j) * GS + m];
-      a[j] = __builtin_bit_cast(__bf16, b);
-      bsum += bf2f(b);
-    }
+    for (int ct = 0; ct < CT; ++ct)
+      bx[ct] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(xT + (16 * ct + r16) * XS + 8 * g));
 #pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      const int nn = 16 * q + r16;
-      const int tap = nn / CIN, c = nn % CIN;
-      bf16x8 b;
+    for (int tap = 0; tap < KT; ++tap) {
+      // rows 8g + j - tap + 8 of the window, j = 0..7: elements e .. e+7 with e = 8 - tap
+      const int e = 8 - tap;
+      u32x4 av;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const uint16_t v = (nn < NN) ? xt[(8 * g + j + tap) * XS + c] : (uint16_t)0;
-        b[j] = __builtin_bit_cast(__bf16, v);
+      for (int q = 0; q < 4; ++q) {
+        const int lo = (e >> 1) + q;
+        av[q] = (e & 1) ? __builtin_amdgcn_alignbit(W[lo + 1 < 8 ? lo + 1 : 7], W[lo], 16) : W[lo];
       }
-      acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
+      const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+      if (tap == HALO) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bsum += bf2f((uint16_t)(av[q] & 0xffffu)) + bf2f((uint16_t)(av[q] >> 16));
+      }
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+        acc[tap * CT + ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bx[ct], acc[tap * CT + ct], 0, 0, 0);
     }
   }
-  // partial sums: part[w][n][nn] (NOUT x NN) then part bias after them
+  // partial sums: part[w][n][tap * CIN + c] (NOUT x NN), then the bias after them
   float* pw = part + (int64_t)blockIdx.x * (NOUT * NN + NOUT);
 #pragma unroll
-  for (int q = 0; q < NT; ++q)
+  for (int tap = 0; tap < KT; ++tap)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = wave * 16 + 4 * g + j;  // output channel
-      const int col = 16 * q + r16;           // (tap, c)
-      if (col < NN) pw[row * NN + col] = acc[q][j];
-    }
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = wave * 16 + 4 * g + j;  // output channel
+        const int c = 16 * ct + r16;
+        if (c < CIN) pw[row * NN + tap * CIN + c] = acc[tap * CT + ct][j];
+      }
   // bias: the four K groups of a channel hold partial sums
   bsum += __shfl_xor(bsum, 16);
   bsum += __shfl_xor(bsum, 32);
@@ -309,19 +348,25 @@ __global__ void k_head_bwd(const float* __restrict__ h, const float* __restrict_
 }
 
 // g = 2 (z - x) / n at held-out points (0 elsewhere), and sum of squares into *loss.
-__global__ void k_mse(const float* __restrict__ z, const float* __restrict__ x, const uint8_t* __restrict__ hold,
-                      int64_t n_elem, float inv_n, float* __restrict__ g, double* __restrict__ loss) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  float sq = 0.f;
-  if (i < n_elem) {
+// Grid-stride over the elements; the squares are summed in FP64 per lane, then
+// per workgroup, with one atomic per workgroup (a bounded grid keeps them few).
+constexpr int kMseBlocks = 1024;
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ z, const float* __restrict__ x,
+                                             const uint8_t* __restrict__ hold, int64_t n_elem, float inv_n,
+                                             float* __restrict__ g, double* __restrict__ loss) {
+  __shared__ double red[4];
+  double sq = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_elem; i += stride) {
     const bool h = hold[i] != 0;
     const float r = h ? z[i] - x[i] : 0.f;
     g[i] = 2.f * r * inv_n;
-    sq = r * r;
+    sq += (double)r * (double)r;
   }
-  // wavefront reduction, one atomic per wavefront
   for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
-  if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, (double)sq);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0 && loss) atomicAdd(loss, red[0] + red[1] + red[2] + red[3]);
 }
 
 // Adam with bias correction on FP32 master weights (n_out, 9, n_in) of which
@@ -365,6 +410,7 @@ using namespace whsnet;
 namespace {
 int st(hipError_t e) { return e == hipSuccess ? 0 : -3; }
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+constexpr int64_t kConvBlocks = 4096;
 bool okc(int c) { return c == 8 || c == 16 || c == 64; }
 }  // namespace
 
@@ -376,12 +422,13 @@ int whs_net_conv_fwd(const uint16_t* in, int cin, const uint16_t* w, const float
   if (mode < 0 || mode > 2 || (mode == 2 && !mask)) return -1;
   if (P == 0) return 0;
   const int ntiles = (int)nblk(T, TM);
-  if (P * ntiles > 0x7fffffffLL) return -2;
+  const int64_t total = P * ntiles;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  dim3 grid((unsigned)(P * ntiles));
+  // enough workgroups to fill the chip several times over; each walks tiles
+  dim3 grid((unsigned)(total < kConvBlocks ? total : kConvBlocks));
   dim3 block(cout == 64 ? 256 : 64);
 #define WHS_CONV(CI, CO, MO) \
-  hipLaunchKernelGGL((k_conv<CI, CO, MO>), grid, block, 0, s, in, w, bias, mask, out, T, ntiles)
+  hipLaunchKernelGGL((k_conv<CI, CO, MO>), grid, block, 0, s, in, w, bias, mask, out, T, ntiles, total)
   if (cin == 8 && cout == 64 && mode == 0) WHS_CONV(8, 64, 0);
   else if (cin == 64 && cout == 64 && mode == 0) WHS_CONV(64, 64, 0);
   else if (cin == 64 && cout == 16 && mode == 1) WHS_CONV(64, 16, 1);
@@ -443,7 +490,8 @@ int whs_net_mse(const float* z, const float* x, const uint8_t* hold, int64_t n_e
                 double* loss, void* stream) {
   if (!z || !x || !hold || !g || n_elem < 0) return -1;
   if (n_elem == 0) return 0;
-  hipLaunchKernelGGL(k_mse, dim3(nblk(n_elem, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), z, x, hold,
+  const int64_t blocks = nblk(n_elem, 256) < kMseBlocks ? nblk(n_elem, 256) : kMseBlocks;
+  hipLaunchKernelGGL(k_mse, dim3((unsigned)blocks), dim3(256), 0, static_cast<hipStream_t>(stream), z, x, hold,
                      n_elem, inv_n, g, loss);
   return st(hipGetLastError());
 }
