@@ -1,0 +1,139 @@
+"""Parity at the measured sizes, in the launch configuration bench.py times.
+
+The workloads are generated exactly as bench.py generates them; the kernels
+run on the whole batch, and sampled series (spread over the batch, the last
+one included) are checked one by one against the oracle.  FP32 storage:
+per-series error <= 1e-4 and componentwise backward error <= 1e-6 for z,
+1e-4 relative for the adjoint (grad_lambda 1e-3) against the oracle's adjoint
+at the kernel's stored z.  Plus the finite-difference check of grad_lambda on
+16 pixels of the headline batch (FP64 storage, central differences)."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import whs_ref as R
+from paper_2604_00048_amd import synth, whs
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def series(t, idx, S=64):
+    """Natural-layout float64 (len(idx), T, C) of sampled series of an interleaved (nb, T, C, S) tensor."""
+    return torch.stack([t[p // S, :, :, p % S] for p in idx]).double().cpu().numpy()
+
+
+def rows(t, idx, S=64):
+    return torch.stack([t[p // S, :, p % S] for p in idx]).cpu().numpy()
+
+
+def sample(P, n=16):
+    idx = np.unique(np.linspace(0, P - 1, n).astype(np.int64))
+    return [int(i) for i in idx]
+
+
+def test_headline_heteroscedastic_fwd_bwd_sampled():
+    P, T, d = 65536, 3288, 2
+    pk = synth.generate_packed("heteroscedastic", P, S=64, dtype=torch.float32, device=DEV, chunk=8192, T=T)
+    g = torch.randn(pk.x.shape, generator=torch.Generator(device=DEV).manual_seed(7), device=DEV, dtype=torch.float32)
+    desc = whs.make_desc(P, T, d, 1, 64, whs.WHS_F32, whs.WHS_LAMBDA_PER_DIFF)
+    ws = torch.empty(whs.workspace_bytes(desc), dtype=torch.uint8, device=DEV)
+    z, info = whs.whs_solve(pk.x, pk.w, pk.lam, d, P, workspace=ws)
+    gx, gl, info2 = whs.whs_backward(pk.w, pk.lam, z, g, d, P, workspace=ws)
+    torch.cuda.synchronize()
+    assert int((info != 0).sum()) == 0 and int((info2 != 0).sum()) == 0
+    idx = sample(P)
+    x = series(pk.x, idx)[:, :, 0]
+    w = rows(pk.w, idx)
+    lam = rows(pk.lam, idx).astype(np.float64)
+    zs = series(z, idx)[:, :, 0]
+    zref, iref = R.solve_band(x, w, lam, d)
+    assert (iref == 0).all()
+    assert R.rel_err(zs, zref).max() <= 1e-4
+    assert R.backward_error(x, w, lam, d, zs).max() <= 1e-6
+    gs = series(g, idx)[:, :, 0]
+    gx_ref, gl_ref, _ = R.vjp(x, w, lam, d, gs, z=zs)
+    egx = np.abs(series(gx, idx)[:, :, 0] - gx_ref).max(1) / np.abs(gx_ref).max(1)
+    egl = np.abs(rows(gl, idx) - gl_ref).max(1) / np.abs(gl_ref).max(1)
+    assert egx.max() <= 1e-4, egx.max()
+    assert egl.max() <= 1e-3, egl.max()
+
+
+def test_headline_grad_lambda_by_finite_differences_on_16_pixels():
+    P, T, d = 65536, 3288, 2
+    pk = synth.generate_packed("heteroscedastic", P, S=64, dtype=torch.float32, device=DEV, chunk=8192, T=T)
+    idx = sample(P)
+    x = torch.stack([pk.x[p // 64, :, :, p % 64] for p in idx]).double()           # (16, T, 1)
+    w = torch.stack([pk.w[p // 64, :, p % 64] for p in idx])
+    lam = torch.stack([pk.lam[p // 64, :, p % 64] for p in idx]).double()
+    n = len(idx)
+    ks = [200 + (T - d - 400) * i // max(n - 1, 1) for i in range(n)]           # one difference row per pixel
+    g = torch.randn((n, T, 1), generator=torch.Generator().manual_seed(3), dtype=torch.float64).to(DEV)
+    # gradients of f(lambda) = sum_t g_t z_t at the 16 pixels
+    xt, wt, lt, gt = (synth.pack_series(x, 64), synth.pack_rows(w, 64), synth.pack_rows(lam, 64),
+                      synth.pack_series(g, 64))
+    z, _ = whs.whs_solve(xt, wt, lt, d, n)
+    _, gl, _ = whs.whs_backward(wt, lt, z, gt, d, n)
+    gl = synth.unpack_rows(gl, n).cpu().numpy()
+    # central differences: rows i (+h) and n+i (-h) of one batch of 2n series
+    lp = lam.repeat(2, 1).clone()
+    h = torch.zeros(n, dtype=torch.float64, device=DEV)
+    for i, k in enumerate(ks):
+        h[i] = 1e-4 * lam[i, k]
+        lp[i, k] += h[i]
+        lp[n + i, k] -= h[i]
+    z2, info = whs.whs_solve(synth.pack_series(x.repeat(2, 1, 1), 64), synth.pack_rows(w.repeat(2, 1), 64),
+                             synth.pack_rows(lp, 64), d, 2 * n)
+    torch.cuda.synchronize()
+    assert int((info != 0).sum()) == 0
+    z2 = synth.unpack_series(z2, 2 * n)[:, :, 0]
+    f = (g[:, :, 0].repeat(2, 1) * z2).sum(1)
+    fd = ((f[:n] - f[n:]) / (2 * h)).cpu().numpy()
+    an = np.array([gl[i, k] for i, k in enumerate(ks)])
+    scale = np.abs(gl).max(1)
+    assert (np.abs(fd - an) <= 1e-5 * scale + 1e-4 * np.abs(an)).all(), np.abs(fd - an) / scale
+
+
+def test_ten_band_forward_sampled():
+    P, T, d, C = 262144, 3288, 2, 10
+    pk = synth.generate_packed("multiband", P, S=64, dtype=torch.float32, device=DEV, chunk=8192, T=T, C=C)
+    z, info = whs.whs_solve(pk.x, pk.w, pk.lam, d, P)
+    torch.cuda.synchronize()
+    assert int((info != 0).sum()) == 0
+    idx = sample(P, 12)
+    x = series(pk.x, idx)
+    w = rows(pk.w, idx)
+    lam = pk.lam[idx].double().cpu().numpy()
+    zs = series(z, idx)
+    zref, iref = R.solve_band(x, w, lam, d)
+    assert (iref == 0).all()
+    assert R.rel_err(zs, zref).max() <= 1e-4
+    assert R.backward_error(x, w, lam, d, zs).max() <= 1e-6
+    del pk, z
+
+
+def test_uneven_batch_plan_sampled():
+    groups = synth.uneven_groups(n_series=100_000, device=DEV)
+    x, w, lam, descs = synth.pack_groups(groups, dtype=torch.float32, device=DEV)
+    z = torch.empty_like(x)
+    N = sum(dd["n_series"] for dd in descs)
+    info = torch.full((N,), -1, dtype=torch.int32, device=DEV)
+    plan = whs.Plan(descs, torch.float32)
+    plan.graph_launch(w, lam, x, z, info)
+    torch.cuda.synchronize()
+    assert int((info != 0).sum()) == 0
+    for dd in descs:
+        n, T, d = dd["n_series"], dd["T"], dd["d"]
+        pick = sample(n, 3)
+        xs = synth.unpack_group(x, dd)[pick].double().cpu().numpy()[:, :, 0]
+        zs = synth.unpack_group(z, dd)[pick].double().cpu().numpy()[:, :, 0]
+        nb = (n + 63) // 64
+        wg = w[dd["w_off"]:dd["w_off"] + nb * T * 64].view(nb, T, 64)
+        ws_ = synth.unpack_rows(wg, n)[pick].cpu().numpy()
+        ls = lam[dd["lam_off"]:dd["lam_off"] + n][pick].double().cpu().numpy()
+        zref, iref = R.solve_band(xs, ws_, ls, d)
+        assert (iref == 0).all()
+        assert R.rel_err(zs, zref).max() <= 1e-4, (T, d)
+        assert R.backward_error(xs, ws_, ls, d, zs).max() <= 1e-6, (T, d)
+    plan.close()
