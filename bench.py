@@ -74,7 +74,33 @@ def _cpu_worker(args):
     return x.shape[0]
 
 
-def cpu_baseline(pk, d: int, n_sample: int, workers: int):
+def _lapack_worker(args):
+    """Forward + adjoint of a chunk of series with LAPACK's banded SPD solver (dpbsv)."""
+    import numpy as np
+    import scipy.linalg
+    from oracle import whs_ref as R
+    x, w, lam, g, d = args
+    AB = R.omega_band(w, lam, d)
+    for p in range(x.shape[0]):
+        z = scipy.linalg.solveh_banded(AB[p], np.where(w[p] != 0, x[p], 0.0), lower=True)
+        u = scipy.linalg.solveh_banded(AB[p], g[p], lower=True)
+        _ = np.where(w[p] != 0, u, 0.0)
+        _ = -(R.apply_D(u[None], d) * R.apply_D(z[None], d))
+    return x.shape[0]
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pk, d: int, n_sample: int, workers: int, worker=None):
     """Time the FP64 oracle (forward + adjoint) on ``n_sample`` series of the same
     inputs, split over ``workers`` processes."""
     import multiprocessing as mp
@@ -90,11 +116,12 @@ def cpu_baseline(pk, d: int, n_sample: int, workers: int):
     g = np.random.default_rng(0).normal(size=x.shape)
     chunks = np.array_split(np.arange(n_sample), workers)
     jobs = [(x[c], w[c], lam[c], g[c], d) for c in chunks if len(c)]
+    fn = worker or _cpu_worker
     ctx = mp.get_context("fork")
     with ctx.Pool(len(jobs)) as pool:
-        pool.map(_cpu_worker, [(j[0][:2], j[1][:2], j[2][:2], j[3][:2], d) for j in jobs])  # warm imports
+        pool.map(fn, [(j[0][:2], j[1][:2], j[2][:2], j[3][:2], d) for j in jobs])  # warm imports
         t0 = time.perf_counter()
-        done = sum(pool.map(_cpu_worker, jobs))
+        done = sum(pool.map(fn, jobs))
         dt = time.perf_counter() - t0
     return done / dt, dt, len(jobs)
 
@@ -327,6 +354,8 @@ def bench_hetero(args):
     fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
     bwd_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
     ms_step = total_ms / K
+    step_ms = sorted(e[0].elapsed_time(e[2]) for e in ev)
+    median_ms = step_ms[K // 2] if K % 2 else 0.5 * (step_ms[K // 2 - 1] + step_ms[K // 2])
     n_fail = int((info != 0).sum().item())
 
     copy_gbs = copy_ceiling(dev)
@@ -370,7 +399,7 @@ def bench_hetero(args):
             "whs_solve": {"ms": fwd_ms, "alg_GBps": fwd_gbs, "frac": fwd_gbs / PEAK_HBM_GBS,
                           "alg_bytes_per_series": fb},
             "whs_backward": {"ms": bwd_ms, "alg_GBps": bwd_gbs, "frac": bwd_gbs / PEAK_HBM_GBS},
-            "step": {"ms": ms_step, "alg_GBps": step_gbs, "frac": step_gbs / PEAK_HBM_GBS},
+            "step": {"ms": ms_step, "median_ms": median_ms, "alg_GBps": step_gbs, "frac": step_gbs / PEAK_HBM_GBS},
         },
         "failed_series": n_fail,
         "wall_s_timed": wall,
@@ -382,7 +411,13 @@ def bench_hetero(args):
         out["cpu_baseline"] = {
             "value": rate, "unit": "series/s", "cores": used, "kind": "oracle",
             "sample": f"{n} of the {P} series (first ones), FP64 numpy banded LDL^T forward + adjoint, "
-                      f"{used} processes, {secs:.1f} s",
+                      f"{used} processes, {secs:.1f} s, host CPU {cpu_model()}",
+        }
+        nl = min(args.cpu_sample // 8, P)
+        rate_l, secs_l, used_l = cpu_baseline(pk, d, nl, workers, worker=_lapack_worker)
+        out["cpu_lapack"] = {
+            "value": rate_l, "unit": "series/s", "cores": used_l, "kind": "LAPACK dpbsv (scipy solveh_banded)",
+            "sample": f"{nl} of the {P} series, forward + adjoint solve per series, {used_l} processes, {secs_l:.1f} s",
         }
     return out
 
