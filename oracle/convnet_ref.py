@@ -155,6 +155,19 @@ def head_backward(h: np.ndarray, glam_rows: np.ndarray, d: int, lo: float = -1.0
     return gh
 
 
+def scalar_head(theta: float, P: int, lo: float = -1.0, hi: float = 5.0) -> np.ndarray:
+    """Homoscedastic model (Sec. IV-B): one learned scalar weight for every series,
+    through the same bounded parametrisation, ``log10 lambda = lo + (hi - lo) sigmoid(theta)``."""
+    return np.full(P, head(np.array([float(theta)]), lo, hi)[0])
+
+
+def scalar_head_backward(theta: float, glam: np.ndarray, lo: float = -1.0, hi: float = 5.0) -> float:
+    """``dL/dtheta`` from the per-series ``dL/dlambda`` (every series shares lambda)."""
+    s = 1.0 / (1.0 + np.exp(-float(theta)))
+    lam = 10.0 ** (lo + (hi - lo) * s)
+    return float(np.sum(glam)) * lam * np.log(10.0) * (hi - lo) * s * (1.0 - s)
+
+
 def masked_mse(z: np.ndarray, x: np.ndarray, mask: np.ndarray):
     """Mean of ``(z - x)^2`` over ``mask`` and its gradient w.r.t. ``z``."""
     m = np.asarray(mask) != 0

@@ -114,3 +114,32 @@ def test_adam_matches_torch():
         opt.step()
         q, m, v = N.adam_step(q, g, m, v, step, 1e-2)
     np.testing.assert_allclose(q, p.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_scalar_head_bounds_and_gradient_through_the_smoother():
+    from oracle import whs_ref as R
+    # midpoint and limits of the bounded parametrisation
+    np.testing.assert_allclose(N.scalar_head(0.0, 3), 10.0 ** 2.0, rtol=1e-14)
+    assert abs(np.log10(N.scalar_head(60.0, 1)[0]) - 5.0) < 1e-12
+    assert abs(np.log10(N.scalar_head(-60.0, 1)[0]) + 1.0) < 1e-12
+    # d/dtheta of the held-out MSE of the smoothed series, every series sharing lambda(theta)
+    r = np.random.default_rng(3)
+    P, T, d = 3, 60, 2
+    x = r.normal(size=(P, T)) * 0.1 + 0.3
+    w = (r.random((P, T)) < 0.4).astype(np.uint8)
+    w[:, :3] = 1
+    hold = ((r.random((P, T)) < 0.3) & (w != 0)).astype(np.uint8)
+    wtr = w * (1 - hold)
+
+    def loss(theta):
+        z, _ = R.solve_band(np.where(wtr != 0, x, 0.0), wtr, N.scalar_head(theta, P), d)
+        return N.masked_mse(z, x, hold)[0]
+
+    theta = 0.3
+    z, _ = R.solve_band(np.where(wtr != 0, x, 0.0), wtr, N.scalar_head(theta, P), d)
+    _, gz = N.masked_mse(z, x, hold)
+    _, glam, _ = R.vjp(np.where(wtr != 0, x, 0.0), wtr, N.scalar_head(theta, P), d, gz, z=z)
+    an = N.scalar_head_backward(theta, glam)
+    h = 1e-5
+    fd = (loss(theta + h) - loss(theta - h)) / (2 * h)
+    assert abs(fd - an) <= 1e-6 * abs(fd) + 1e-12, (fd, an)
