@@ -65,6 +65,16 @@ int whs_net_head_fwd(const float* h, int64_t P, int T, int S, int d, float lo, f
 int whs_net_head_bwd(const float* h, const float* glam, int64_t P, int T, int S, int d, float lo, float hi,
                      uint16_t* gh16, void* stream);
 
+/* Homoscedastic model (Sec. IV-B): one learned scalar theta (device FP32[1])
+ * gives the same weight to every series, log10 lambda = lo + (hi - lo)
+ * sigmoid(theta).  fwd writes lambda (FP32[P], the scalar-weight layout of
+ * whs_solve); bwd writes dL/dtheta (FP32[1]) = sum_p glam[p] dlambda/dtheta
+ * from whs_backward's per-series grad_lambda (FP32[P]), summed in FP64 by one
+ * workgroup in a fixed order (deterministic).  -1 on invalid arguments. */
+int whs_net_scalar_head_fwd(const float* theta, int64_t P, float lo, float hi, float* lam, void* stream);
+int whs_net_scalar_head_bwd(const float* theta, const float* glam, int64_t P, float lo, float hi,
+                            float* grad_theta, void* stream);
+
 /* Masked MSE (Sec. IV-C, Sec. IV-D): g = 2 (z - x) inv_n where hold != 0,
  * else 0; *loss += sum of (z - x)^2 over hold (FP64, may be NULL). */
 int whs_net_mse(const float* z, const float* x, const uint8_t* hold, int64_t n_elem, float inv_n, float* g,

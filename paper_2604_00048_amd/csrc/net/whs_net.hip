@@ -369,6 +369,34 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ z, const 
   if (threadIdx.x == 0 && loss) atomicAdd(loss, red[0] + red[1] + red[2] + red[3]);
 }
 
+// Homoscedastic head: every series gets lambda = 10^(lo + (hi - lo) sigmoid(theta)).
+__global__ void k_scalar_head_fwd(const float* __restrict__ theta, int64_t P, float lo, float hi,
+                                  float* __restrict__ lam) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const double s = 1.0 / (1.0 + exp(-(double)theta[0]));
+  lam[i] = (float)exp10((double)lo + ((double)hi - (double)lo) * s);
+}
+
+// dL/dtheta = (sum_p glam[p]) dlambda/dtheta; one workgroup, FP64, fixed order.
+__global__ __launch_bounds__(1024) void k_scalar_head_bwd(const float* __restrict__ theta,
+                                                          const float* __restrict__ glam, int64_t P, float lo,
+                                                          float hi, float* __restrict__ grad) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < P; i += blockDim.x) s += (double)glam[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) tot += red[wv];
+    const double sg = 1.0 / (1.0 + exp(-(double)theta[0]));
+    const double lam = exp10((double)lo + ((double)hi - (double)lo) * sg);
+    grad[0] = (float)(tot * lam * 2.302585092994046 * ((double)hi - (double)lo) * sg * (1.0 - sg));
+  }
+}
+
 // Adam with bias correction on FP32 master weights (n_out, 9, n_in) of which
 // the first n_real output rows are trained; writes the bfloat16 forward copy
 // (n_out_pad, 9, n_in) and the transposed, tap-flipped copy used by the
@@ -483,6 +511,22 @@ int whs_net_head_bwd(const float* h, const float* glam, int64_t P, int T, int S,
   if (P == 0) return 0;
   hipLaunchKernelGGL(k_head_bwd, dim3(nblk(P * T, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), h, glam, P,
                      T, S, d, lo, hi, gh16);
+  return st(hipGetLastError());
+}
+
+int whs_net_scalar_head_fwd(const float* theta, int64_t P, float lo, float hi, float* lam, void* stream) {
+  if (!theta || !lam || P < 0 || !(hi > lo)) return -1;
+  if (P == 0) return 0;
+  hipLaunchKernelGGL(k_scalar_head_fwd, dim3(nblk(P, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), theta,
+                     P, lo, hi, lam);
+  return st(hipGetLastError());
+}
+
+int whs_net_scalar_head_bwd(const float* theta, const float* glam, int64_t P, float lo, float hi,
+                            float* grad_theta, void* stream) {
+  if (!theta || !glam || !grad_theta || P < 1 || !(hi > lo)) return -1;
+  hipLaunchKernelGGL(k_scalar_head_bwd, dim3(1), dim3(1024), 0, static_cast<hipStream_t>(stream), theta, glam, P,
+                     lo, hi, grad_theta);
   return st(hipGetLastError());
 }
 

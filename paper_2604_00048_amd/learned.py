@@ -88,6 +88,51 @@ class Learned:
         return loss.item() / max(batch.n_hold, 1) / self.sd ** 2
 
 
+class LearnedScalar:
+    """Homoscedastic model (Sec. IV-B): one learned weight shared by every series,
+    through the same bounded parametrisation as the per-day head."""
+
+    def __init__(self, device, theta0: float = 0.0):
+        self.device = torch.device(device)
+        self.theta = torch.full((1,), theta0, dtype=torch.float32, device=self.device)
+        self.m = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self.v = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self.step = 0
+
+    def weights(self, batch: Batch):
+        return net.scalar_head_fwd(self.theta, batch.P)
+
+    def train_step(self, batch: Batch, lr: float, sd: float) -> float:
+        lam = self.weights(batch)
+        z, _ = whs.whs_solve(batch.x_train, batch.w_train, lam, D, batch.P)
+        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        g = net.mse(z, batch.x_true, batch.hold, 1.0 / (max(batch.n_hold, 1) * sd ** 2), loss=loss)
+        _, glam, _ = whs.whs_backward(batch.w_train, lam, z, g, D, batch.P, need_x=False)
+        gt = net.scalar_head_bwd(self.theta, glam, batch.P)
+        self.step += 1
+        net._chk(net.lib().whs_net_adam(net._p(self.theta), net._p(gt), net._p(self.m), net._p(self.v), 1, lr, 0.9,
+                                        0.999, 1e-8, self.step, net._s(self.device)), "whs_net_adam")
+        return loss.item() / max(batch.n_hold, 1) / sd ** 2
+
+    def log10_lambda(self) -> float:
+        return math.log10(net.scalar_head_fwd(self.theta, 1).item())
+
+
+def train_scalar(device, steps: int = 400, batch_size: int = 4096, lr: float = 3e-2, seed: int = 2604004805,
+                 log=None) -> LearnedScalar:
+    """Train the one shared weight through the smoother on the same batches as ``train``."""
+    first = make_batch(batch_size, seed, 0, device)
+    _, sd = input_stats(first)
+    L = LearnedScalar(device)
+    for s in range(steps):
+        b = first if s == 0 else make_batch(batch_size, seed, s, device)
+        lr_s = lr * 0.5 * (1.0 + math.cos(math.pi * s / steps))
+        loss = L.train_step(b, lr_s, sd)
+        if log and (s % 50 == 0 or s == steps - 1):
+            log(f"scalar step {s} loss {loss:.4f} log10 lambda {L.log10_lambda():.3f}")
+    return L
+
+
 def heldout_sse(z: torch.Tensor, batch: Batch) -> float:
     loss = torch.zeros(1, dtype=torch.float64, device=z.device)
     net.mse(z, batch.x_true, batch.hold, 1.0, loss=loss)
@@ -109,10 +154,12 @@ def train(device, steps: int = 400, batch_size: int = 4096, lr: float = 1e-3, se
     return L
 
 
-def evaluate(L: Learned, device, n_series: int = 262144, chunk: int = 16384, seed: int = 2604004806):
-    """Held-out RMSE (data units) and throughput of the learned and the plain forms on fresh series."""
+def evaluate(L: Learned, device, n_series: int = 262144, chunk: int = 16384, seed: int = 2604004806,
+             Ls: LearnedScalar | None = None):
+    """Held-out RMSE (data units) and throughput of the learned and the plain forms on fresh series
+    (and of the learned shared weight, if given)."""
     grid = torch.tensor(GRID, dtype=torch.float64, device=device)
-    sse_l = sse_p = 0.0
+    sse_l = sse_p = sse_s = 0.0
     n = 0
     t_l = t_p = 0.0
     lam_dev = []
@@ -133,9 +180,12 @@ def evaluate(L: Learned, device, n_series: int = 262144, chunk: int = 16384, see
         t_p += t2 - t1
         sse_l += heldout_sse(z_l, b)
         sse_p += heldout_sse(z_p, b)
+        if Ls is not None:
+            z_s, _ = whs.whs_solve(b.x_train, b.w_train, Ls.weights(b), D, P)
+            sse_s += heldout_sse(z_s, b)
         n += b.n_hold
         lam_dev.append(torch.log10(lam_best.double()).mean().item())
-    return {
+    out = {
         "n_series": n_series,
         "heldout_points": n,
         "rmse_learned": math.sqrt(sse_l / n),
@@ -145,3 +195,7 @@ def evaluate(L: Learned, device, n_series: int = 262144, chunk: int = 16384, see
         "series_per_s_plain_gcv": n_series / t_p,
         "mean_log10_lambda_gcv": sum(lam_dev) / len(lam_dev),
     }
+    if Ls is not None:
+        out["rmse_learned_scalar"] = math.sqrt(sse_s / n)
+        out["log10_lambda_learned_scalar"] = Ls.log10_lambda()
+    return out

@@ -39,6 +39,8 @@ NET_SIGNATURES = {
     "whs_net_mse": (_I32, [_VP, _VP, _VP, _I64, _F, _VP, _VP, _VP]),
     "whs_net_adam": (_I32, [_VP, _VP, _VP, _VP, _I64, _F, _F, _F, _F, _I32, _VP]),
     "whs_net_pack_weights": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP, _VP]),
+    "whs_net_scalar_head_fwd": (_I32, [_VP, _I64, _F, _F, _VP, _VP]),
+    "whs_net_scalar_head_bwd": (_I32, [_VP, _VP, _I64, _F, _F, _VP, _VP]),
 }
 
 _net = None
@@ -195,6 +197,22 @@ def head_bwd(h, glam, P, T, S, d, out=None, lo=LO, hi=HI):
         out = torch.empty((P, T, 16), dtype=torch.int16, device=h.device)
     _chk(lib().whs_net_head_bwd(_p(h), _p(glam), P, T, S, d, lo, hi, _p(out), _s(h.device)), "whs_net_head_bwd")
     return out
+
+
+def scalar_head_fwd(theta, P, lam=None, lo=LO, hi=HI):
+    """One weight for every series from the scalar parameter ``theta`` (FP32[1])."""
+    if lam is None:
+        lam = torch.empty(P, dtype=torch.float32, device=theta.device)
+    _chk(lib().whs_net_scalar_head_fwd(_p(theta), P, lo, hi, _p(lam), _s(theta.device)), "whs_net_scalar_head_fwd")
+    return lam
+
+
+def scalar_head_bwd(theta, glam, P, grad=None, lo=LO, hi=HI):
+    if grad is None:
+        grad = torch.empty(1, dtype=torch.float32, device=theta.device)
+    _chk(lib().whs_net_scalar_head_bwd(_p(theta), _p(glam), P, lo, hi, _p(grad), _s(theta.device)),
+         "whs_net_scalar_head_bwd")
+    return grad
 
 
 def mse(z, x, hold, inv_n, g=None, loss=None):

@@ -16,3 +16,17 @@ def test_learned_weights_beat_gcv_on_fresh_series():
     ev = learned.evaluate(L, dev, n_series=16384, chunk=16384)
     print(ev)
     assert ev["rmse_learned"] < ev["rmse_plain_gcv"], ev
+
+
+def test_learned_shared_weight_improves_on_its_start():
+    # the homoscedastic model: one weight for every series, trained through the smoother
+    dev = torch.device("cuda:0")
+    L0 = learned.LearnedScalar(dev)
+    Ls = learned.train_scalar(dev, steps=100, batch_size=4096, log=print)
+    b = learned.make_batch(8192, 2604004806, 0, dev)
+    from paper_2604_00048_amd import whs
+    z0, _ = whs.whs_solve(b.x_train, b.w_train, L0.weights(b), learned.D, b.P)
+    z1, _ = whs.whs_solve(b.x_train, b.w_train, Ls.weights(b), learned.D, b.P)
+    e0, e1 = learned.heldout_sse(z0, b), learned.heldout_sse(z1, b)
+    print(L0.log10_lambda(), Ls.log10_lambda(), e0, e1)
+    assert e1 < e0

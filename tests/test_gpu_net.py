@@ -175,3 +175,16 @@ def test_whole_network_forward_backward():
         gb = g[cop * 9 * cin:cop * 9 * cin + co]
         assert rel(gw, grads[i][0]) < 2e-2, i
         assert rel(gb, grads[i][1]) < 2e-2, i
+
+
+def test_scalar_head_kernels():
+    Pn = 1000
+    for theta in (-3.0, 0.0, 0.7, 4.0):
+        th = torch.tensor([theta], dtype=torch.float32, device=dev)
+        lam = net.scalar_head_fwd(th, Pn).cpu().double().numpy()
+        ref = N.scalar_head(np.float32(theta), Pn)
+        assert np.max(np.abs(lam / ref - 1)) < 1e-6
+        glam = rng.normal(size=Pn).astype(np.float32)
+        gt = net.scalar_head_bwd(th, torch.tensor(glam, device=dev), Pn).item()
+        gref = N.scalar_head_backward(np.float32(theta), glam.astype(np.float64))
+        assert abs(gt - gref) <= 1e-5 * abs(gref) + 1e-30, (gt, gref)
