@@ -214,13 +214,13 @@ def bench_learned(args):
     from paper_2604_00048_amd import learned
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    L = learned.train(dev, steps=args.train_steps, batch_size=4096, lr=args.lr,
+    L = learned.train(dev, steps=args.train_steps, batch_size=4096, lr=args.lr, clouds=args.clouds,
                       log=lambda m: print("# " + m, file=sys.stderr, flush=True))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    Ls = learned.train_scalar(dev, steps=args.train_steps, batch_size=4096,
+    Ls = learned.train_scalar(dev, steps=args.train_steps, batch_size=4096, clouds=args.clouds,
                               log=lambda m: print("# " + m, file=sys.stderr, flush=True))
-    ev = learned.evaluate(L, dev, n_series=args.eval_series, Ls=Ls)
+    ev = learned.evaluate(L, dev, n_series=args.eval_series, Ls=Ls, clouds=args.clouds)
     return {
         "metric": "held-out RMSE (learned per-day lambda vs GCV scalar lambda), T=3288, d=2",
         "value": ev["rmse_learned"], "unit": "reflectance RMSE", "n_gpus": 1, "steps": args.train_steps,
@@ -230,7 +230,7 @@ def bench_learned(args):
                                f"model): 4-layer conv net (kernel 9, 64 channels, BF16 MFMA) trained "
                                f"{args.train_steps} steps of 4096 series through the smoother, evaluated on "
                                f"{args.eval_series} fresh series against GCV over 21 scalar weights",
-                   "train_steps": args.train_steps, "lr": args.lr},
+                   "train_steps": args.train_steps, "lr": args.lr, "clouds": args.clouds},
         "heldout": ev,
         "train_seconds": t_train,
     }
@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--retune", action="store_true")
     ap.add_argument("--train-steps", type=int, default=400)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--clouds", type=float, default=0.0,
+                    help="learned workload: fraction of acquisitions cloud-contaminated and kept as observed")
     ap.add_argument("--eval-series", type=int, default=262144)
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")

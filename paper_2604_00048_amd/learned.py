@@ -35,21 +35,33 @@ class Batch:
     x_true: torch.Tensor    # interleaved observations (targets at held-out points)
     hold: torch.Tensor      # interleaved held-out mask
     n_hold: int
+    x_clean: torch.Tensor | None = None   # interleaved noise-free signal (cloud experiments)
 
 
-def make_batch(P: int, seed: int, chunk: int, device, T: int = T_DAYS, frac: float = 0.1) -> Batch:
-    """One batch of the nine-year daily generator (band 0), with a held-out split."""
+def make_batch(P: int, seed: int, chunk: int, device, T: int = T_DAYS, frac: float = 0.1,
+               clouds: float = 0.0) -> Batch:
+    """One batch of the nine-year daily generator (band 0), with a held-out split.
+
+    ``clouds > 0``: that fraction of the acquisitions is cloud-contaminated and
+    still marked observed (the cloud mask is withheld, Sec. IV-C); the held-out
+    targets are the observed values, as in training on real series, and the
+    noise-free signal is kept for evaluation."""
     b = synth.multiband_homoscedastic(P, T=T, C=1, d=D, seed=seed, device=device, chunk=chunk)
     gen = synth._gen(seed * 7 + chunk * 13 + 1, device)
+    x_obs = b.x
+    if clouds > 0:
+        x_obs, _ = synth.cloud_contaminate(b.x, b.w, clouds, synth._gen(seed * 11 + chunk * 17 + 5, device))
+        x_obs = synth._finish(x_obs, b.w)
     hold = synth.holdout_split(b.w, frac, gen)
     w_tr = (b.w != 0) & (hold == 0)
-    x_tr = torch.where(w_tr[:, :, None], b.x, torch.zeros((), dtype=b.x.dtype, device=b.x.device))
+    x_tr = torch.where(w_tr[:, :, None], x_obs, torch.zeros((), dtype=b.x.dtype, device=b.x.device))
     return Batch(P=P,
                  x_train=synth.pack_series(x_tr.float(), S),
                  w_train=synth.pack_rows(w_tr.to(torch.uint8), S),
-                 x_true=synth.pack_series(b.x.float(), S),
+                 x_true=synth.pack_series(x_obs.float(), S),
                  hold=synth.pack_rows(hold, S),
-                 n_hold=int(hold.sum().item()))
+                 n_hold=int(hold.sum().item()),
+                 x_clean=synth.pack_series(b.clean.float(), S) if clouds > 0 else None)
 
 
 def input_stats(batch: Batch):
@@ -119,13 +131,13 @@ class LearnedScalar:
 
 
 def train_scalar(device, steps: int = 400, batch_size: int = 4096, lr: float = 3e-2, seed: int = 2604004805,
-                 log=None) -> LearnedScalar:
+                 log=None, clouds: float = 0.0) -> LearnedScalar:
     """Train the one shared weight through the smoother on the same batches as ``train``."""
-    first = make_batch(batch_size, seed, 0, device)
+    first = make_batch(batch_size, seed, 0, device, clouds=clouds)
     _, sd = input_stats(first)
     L = LearnedScalar(device)
     for s in range(steps):
-        b = first if s == 0 else make_batch(batch_size, seed, s, device)
+        b = first if s == 0 else make_batch(batch_size, seed, s, device, clouds=clouds)
         lr_s = lr * 0.5 * (1.0 + math.cos(math.pi * s / steps))
         loss = L.train_step(b, lr_s, sd)
         if log and (s % 50 == 0 or s == steps - 1):
@@ -133,20 +145,20 @@ def train_scalar(device, steps: int = 400, batch_size: int = 4096, lr: float = 3
     return L
 
 
-def heldout_sse(z: torch.Tensor, batch: Batch) -> float:
+def heldout_sse(z: torch.Tensor, batch: Batch, target: torch.Tensor | None = None) -> float:
     loss = torch.zeros(1, dtype=torch.float64, device=z.device)
-    net.mse(z, batch.x_true, batch.hold, 1.0, loss=loss)
+    net.mse(z, batch.x_true if target is None else target, batch.hold, 1.0, loss=loss)
     return loss.item()
 
 
 def train(device, steps: int = 400, batch_size: int = 4096, lr: float = 1e-3, seed: int = 2604004805,
-          log=None) -> Learned:
+          log=None, clouds: float = 0.0) -> Learned:
     """Train the network end to end through the smoother (Adam; cosine-decayed learning rate)."""
-    first = make_batch(batch_size, seed, 0, device)
+    first = make_batch(batch_size, seed, 0, device, clouds=clouds)
     mean, sd = input_stats(first)
     L = Learned(device, mean, sd)
     for s in range(steps):
-        b = first if s == 0 else make_batch(batch_size, seed, s, device)
+        b = first if s == 0 else make_batch(batch_size, seed, s, device, clouds=clouds)
         lr_s = lr * 0.5 * (1.0 + math.cos(math.pi * s / steps))
         loss = L.train_step(b, lr_s)
         if log and (s % 50 == 0 or s == steps - 1):
@@ -155,17 +167,18 @@ def train(device, steps: int = 400, batch_size: int = 4096, lr: float = 1e-3, se
 
 
 def evaluate(L: Learned, device, n_series: int = 262144, chunk: int = 16384, seed: int = 2604004806,
-             Ls: LearnedScalar | None = None):
+             Ls: LearnedScalar | None = None, clouds: float = 0.0):
     """Held-out RMSE (data units) and throughput of the learned and the plain forms on fresh series
     (and of the learned shared weight, if given)."""
     grid = torch.tensor(GRID, dtype=torch.float64, device=device)
     sse_l = sse_p = sse_s = 0.0
+    cl_l = cl_p = cl_s = 0.0
     n = 0
     t_l = t_p = 0.0
     lam_dev = []
     for i, p0 in enumerate(range(0, n_series, chunk)):
         P = min(chunk, n_series - p0)
-        b = make_batch(P, seed, i, device)
+        b = make_batch(P, seed, i, device, clouds=clouds)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, lam = L.weights(b)
@@ -183,6 +196,11 @@ def evaluate(L: Learned, device, n_series: int = 262144, chunk: int = 16384, see
         if Ls is not None:
             z_s, _ = whs.whs_solve(b.x_train, b.w_train, Ls.weights(b), D, P)
             sse_s += heldout_sse(z_s, b)
+        if b.x_clean is not None:
+            cl_l += heldout_sse(z_l, b, b.x_clean)
+            cl_p += heldout_sse(z_p, b, b.x_clean)
+            if Ls is not None:
+                cl_s += heldout_sse(z_s, b, b.x_clean)
         n += b.n_hold
         lam_dev.append(torch.log10(lam_best.double()).mean().item())
     out = {
@@ -198,4 +216,11 @@ def evaluate(L: Learned, device, n_series: int = 262144, chunk: int = 16384, see
     if Ls is not None:
         out["rmse_learned_scalar"] = math.sqrt(sse_s / n)
         out["log10_lambda_learned_scalar"] = Ls.log10_lambda()
+    if clouds > 0:
+        # error against the noise-free signal at the held-out days (cloudy or not)
+        out["clouds"] = clouds
+        out["rmse_clean_learned"] = math.sqrt(cl_l / n)
+        out["rmse_clean_plain_gcv"] = math.sqrt(cl_p / n)
+        if Ls is not None:
+            out["rmse_clean_learned_scalar"] = math.sqrt(cl_s / n)
     return out

@@ -252,6 +252,21 @@ def uneven_groups(n_series=100_000, seed=SEED_BASE + 4, lengths=(365, 730, 1461,
     return groups
 
 
+def cloud_contaminate(x: torch.Tensor, w: torch.Tensor, frac: float, gen):
+    """Cloud-contaminated acquisitions kept as observed (their mask withheld):
+    each observed sample is cloudy with probability ``frac``; a cloudy value is
+    pulled towards a low cloud value, ``x (1 - a) + a c`` with opacity
+    ``a ~ U[0.5, 1]`` and ``c ~ U[-0.05, 0.1]`` (a vegetation index drops
+    under clouds).  ``x (P, T, C)``; returns ``(x_observed, cloudy (P, T) uint8)``."""
+    P, T, C = x.shape
+    dev = x.device
+    cloudy = ((torch.rand((P, T), generator=gen, device=dev, dtype=torch.float64) < frac) & (w != 0))
+    a = _u(gen, (P, T, 1), 0.5, 1.0, dev).to(x.dtype)
+    c = _u(gen, (P, T, 1), -0.05, 0.1, dev).to(x.dtype)
+    xo = torch.where(cloudy[:, :, None], x * (1 - a) + a * c, x)
+    return xo, cloudy.to(torch.uint8)
+
+
 def holdout_split(w: torch.Tensor, frac: float, gen) -> torch.Tensor:
     """Per series, ``round(frac * m)`` observed points chosen uniformly without
     replacement; returns the held-out mask (uint8), a subset of ``w``."""
