@@ -181,3 +181,24 @@ def test_uneven_time_validation():
                                1 << 30, None) == -1
     empty = whs.make_desc(0, 50, 2, 1, 64, 0, 1)
     assert L.whs_solve_coef(ctypes.byref(empty), None, None, None, None, None, None, None, 0, None) == 0
+
+
+def test_network_entry_points_validate_arguments():
+    from paper_2604_00048_amd import net
+    L = net.lib()
+    # unsupported channel pairs and modes, null pointers, negative sizes
+    assert L.whs_net_conv_fwd(FAKE, 32, FAKE, FAKE, 64, 0, None, FAKE, 4, 100, None) == -1
+    assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 2, None, FAKE, 4, 100, None) == -1   # mode 2 needs a mask
+    assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 3, None, FAKE, 4, 100, None) == -1
+    assert L.whs_net_conv_fwd(FAKE, 8, FAKE, FAKE, 16, 1, None, FAKE, 4, 100, None) == -2    # no such layer
+    assert L.whs_net_conv_fwd(None, 64, FAKE, FAKE, 64, 0, None, FAKE, 4, 100, None) == -1
+    assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 0, None, FAKE, 0, 100, None) == 0      # empty batch
+    n = L.whs_net_wgrad_workspace_bytes(64, 64, 7)
+    assert n == 7 * (64 * 9 * 64 + 64) * 4
+    assert L.whs_net_conv_wgrad(FAKE, 64, FAKE, 64, FAKE, FAKE, n - 1, 7, 4, 100, None) == -4
+    assert L.whs_net_conv_wgrad(FAKE, 64, FAKE, 32, FAKE, FAKE, n, 7, 4, 100, None) == -1
+    assert L.whs_net_head_fwd(FAKE, 4, 2, 64, 2, -1.0, 5.0, FAKE, None) == -1                # T <= d
+    assert L.whs_net_mse(None, FAKE, FAKE, 10, 1.0, FAKE, None, None) == -1
+    assert L.whs_net_adam(FAKE, FAKE, FAKE, FAKE, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1   # step >= 1
+    assert L.whs_net_scalar_head_fwd(FAKE, 10, 5.0, -1.0, FAKE, None) == -1                    # hi > lo
+    assert L.whs_net_scalar_head_bwd(FAKE, FAKE, 0, -1.0, 5.0, FAKE, None) == -1               # P >= 1
