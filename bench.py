@@ -244,6 +244,7 @@ def main():
     ap.add_argument("--workload", default="hetero", choices=["hetero", "multiband", "uneven", "learned"])
     ap.add_argument("--P", type=int, default=None)
     ap.add_argument("--T", type=int, default=3288)
+    ap.add_argument("--d", type=int, default=2, help="difference order of the heteroscedastic workload")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--interleave", type=int, default=64)
     ap.add_argument("--n-uneven", type=int, default=100000)
@@ -316,9 +317,9 @@ def bench_hetero(args):
     import torch
     from paper_2604_00048_amd import synth, whs
     dev = torch.device("cuda:0")
-    d, S, P, T = 2, args.interleave, args.P, args.T
+    d, S, P, T = args.d, args.interleave, args.P, args.T
     t_gen = time.perf_counter()
-    pk = synth.generate_packed("heteroscedastic", P, S=S, dtype=torch.float32, device=dev, chunk=8192, T=T)
+    pk = synth.generate_packed("heteroscedastic", P, S=S, dtype=torch.float32, device=dev, chunk=8192, T=T, d=d)
     g = torch.randn(pk.x.shape, generator=torch.Generator(device=dev).manual_seed(7), device=dev,
                     dtype=torch.float32)
     z = torch.empty_like(pk.x)
@@ -384,7 +385,7 @@ def bench_hetero(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "heteroscedastic smoother fwd+bwd: P=65536 series, T=3288 daily steps, d=2, C=1 band, "
+            "workload": f"heteroscedastic smoother fwd+bwd: P={P} series, T={T} daily steps, d={d}, C=1 band, "
                         "per-difference lambda (log10 GP field), FP32 storage / FP64 arithmetic",
             "P": P, "T": T, "d": d, "C": 1, "storage": "f32", "interleave": S,
         },

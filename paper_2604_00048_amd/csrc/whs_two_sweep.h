@@ -415,17 +415,21 @@ __global__ __launch_bounds__(256) void k_two_sweep(Args a) {
 // host-side launchers
 // ---------------------------------------------------------------------------
 
-// Steps per tile.  The uneven-time kernels also carry a window of D's rows,
-// so they use shallower tiles to stay clear of register spills.
-template <int D, int C, bool TAB = false>
+// Steps per tile: the deepest tile whose kernel compiles without register
+// spills for this order, band group and storage type (ES bytes per value).
+// The uneven-time kernels also carry a window of D's rows.
+template <int D, int C, bool TAB = false, int ES = 4>
 constexpr int tile_depth() {
-  if (TAB) return C == 1 ? 16 : 8;
-  return C == 1 ? 24 : 8;
+  if (C != 1) return 8;
+  if (TAB) return D <= 2 ? 16 : 12;
+  if (D <= 2) return ES == 4 ? 24 : 16;
+  if (D == 3) return ES == 4 ? 16 : 12;
+  return 12;
 }
 
 template <int D, int C, typename TS, Src SRC, Mode MODE, bool PERDIFF, bool TAB = false>
 hipError_t launch_fast(const LaunchDesc& L, int c0, int write_info, hipStream_t stream) {
-  constexpr int B = tile_depth<D, C, TAB>();
+  constexpr int B = tile_depth<D, C, TAB, (int)sizeof(TS)>();
   FastArgs f;
   f.P = L.P;
   f.T = L.T;
@@ -453,7 +457,7 @@ hipError_t launch_fast(const LaunchDesc& L, int c0, int write_info, hipStream_t 
 
 template <int D, int C, typename TS, Src SRC, Mode MODE, bool PERDIFF>
 hipError_t launch_generic(const LaunchDesc& L, int c0, int write_info, hipStream_t stream) {
-  constexpr int B = tile_depth<D, C>();
+  constexpr int B = tile_depth<D, C, false, (int)sizeof(TS)>();
   Args a;
   a.P = L.P;
   a.T = L.T;
@@ -479,9 +483,13 @@ hipError_t launch_generic(const LaunchDesc& L, int c0, int write_info, hipStream
   return hipGetLastError();
 }
 
+// checkpoint bytes of one band group, for either storage type (the shallower
+// tile of the two decides)
 template <int D, int C, bool TAB = false>
 size_t ck_bytes_for(int64_t nb, int S, int T) {
-  constexpr int B = tile_depth<D, C, TAB>();
+  constexpr int B4 = tile_depth<D, C, TAB, 4>();
+  constexpr int B8 = tile_depth<D, C, TAB, 8>();
+  constexpr int B = B4 < B8 ? B4 : B8;
   const int64_t nt = (T + B - 1) / B;
   return (size_t)nb * nt * ck_fields<D, C>() * S * sizeof(double);
 }
