@@ -157,11 +157,11 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
 //   gW[n][tap][c] = sum_u gy[u-tap+4][n] in[u][c]
 // so the input operand (columns c, 32 consecutive u) is the same for all
 // nine taps and the tap only shifts the gradient operand.  Each work item is
-// 32 time rows of one series, staged in LDS transposed (channel-major) so
-// every operand fragment is one aligned 16-byte read: the input fragments
-// directly, and each tap's gradient fragment is cut from a 16-element window
-// with funnel shifts.  Workgroup w writes partial sums to part[w];
-// k_wgrad_reduce adds them in a fixed order (deterministic).
+// 32 time rows of one series, staged in LDS transposed (channel-major, pairs
+// of time rows per 4-byte store) so every operand fragment is a contiguous
+// read: the input fragments directly, and each tap's gradient fragment is cut
+// from a 16-element window with funnel shifts.  Workgroup w writes partial
+// sums to part[w]; k_wgrad_reduce adds them in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
 template <int CIN, int NOUT>
 __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ in, const uint16_t* __restrict__ gy,
@@ -171,11 +171,15 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ in, 
   constexpr int NT = KT * CT;                // accumulator tiles per wave
   constexpr int TK = 32;                     // time rows per item
   constexpr int GR = TK + 2 * HALO;          // gradient rows per item
-  constexpr int XS = TK + 8;                 // LDS row strides in bf16 (multiples of 8: aligned 16-byte reads)
-  constexpr int GS = GR + 8;
+  // LDS row strides in bf16: 4 mod 8, so channel rows 8 apart fall 16 banks apart
+  // (the staging stores of one instruction spread over all banks); fragments are
+  // then read as 8-byte pieces
+  constexpr int XS = TK + 12;
+  constexpr int GS = GR + 4;
   constexpr int XROWS = CT * 16;             // channel rows of xT (zero rows pad CIN = 8)
   __shared__ __attribute__((aligned(16))) uint16_t xT[XROWS * XS];
   __shared__ __attribute__((aligned(16))) uint16_t gT[NOUT * GS];
+  typedef __attribute__((ext_vector_type(2))) uint32_t u32x2;
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -199,40 +203,52 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ in, 
     const uint16_t* ip = in + p * (int64_t)T * CIN;
     const uint16_t* gp = gy + p * (int64_t)T * NOUT;
     __syncthreads();
-    // input rows t0 .. t0+31, 8 channels per 16-byte load, stored channel-major
-    for (int i = threadIdx.x; i < TK * (CIN / 8); i += blockDim.x) {
-      const int u = i / (CIN / 8), c0 = 8 * (i % (CIN / 8));
-      const int t = t0 + u;
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (t < T) v = *reinterpret_cast<const u32x4*>(ip + (int64_t)t * CIN + c0);
+    // input rows t0 .. t0+31: a unit is a pair of rows x 8 channels (two 16-byte
+    // loads); it stores 8 dwords, each the (t, t+1) pair of one channel
+    for (int i = threadIdx.x; i < (TK / 2) * (CIN / 8); i += blockDim.x) {
+      const int up = i % (TK / 2), c0 = 8 * (i / (TK / 2));
+      const int t = t0 + 2 * up;
+      u32x4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
+      if (t < T) v0 = *reinterpret_cast<const u32x4*>(ip + (int64_t)t * CIN + c0);
+      if (t + 1 < T) v1 = *reinterpret_cast<const u32x4*>(ip + (int64_t)(t + 1) * CIN + c0);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        xT[(c0 + 2 * q) * XS + u] = (uint16_t)(v[q] & 0xffffu);
-        xT[(c0 + 2 * q + 1) * XS + u] = (uint16_t)(v[q] >> 16);
+        *reinterpret_cast<uint32_t*>(xT + (c0 + 2 * q) * XS + 2 * up) = (v0[q] & 0xffffu) | (v1[q] << 16);
+        *reinterpret_cast<uint32_t*>(xT + (c0 + 2 * q + 1) * XS + 2 * up) = (v0[q] >> 16) | (v1[q] & 0xffff0000u);
       }
     }
-    // gradient rows t0-4 .. t0+35
-    for (int i = threadIdx.x; i < GR * (NOUT / 8); i += blockDim.x) {
-      const int r = i / (NOUT / 8), n0 = 8 * (i % (NOUT / 8));
-      const int t = t0 - HALO + r;
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (t >= 0 && t < T) v = *reinterpret_cast<const u32x4*>(gp + (int64_t)t * NOUT + n0);
+    // gradient rows t0-4 .. t0+35, the same way
+    for (int i = threadIdx.x; i < (GR / 2) * (NOUT / 8); i += blockDim.x) {
+      const int rp = i % (GR / 2), n0 = 8 * (i / (GR / 2));
+      const int t = t0 - HALO + 2 * rp;
+      u32x4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
+      if (t >= 0 && t < T) v0 = *reinterpret_cast<const u32x4*>(gp + (int64_t)t * NOUT + n0);
+      if (t + 1 >= 0 && t + 1 < T) v1 = *reinterpret_cast<const u32x4*>(gp + (int64_t)(t + 1) * NOUT + n0);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        gT[(n0 + 2 * q) * GS + r] = (uint16_t)(v[q] & 0xffffu);
-        gT[(n0 + 2 * q + 1) * GS + r] = (uint16_t)(v[q] >> 16);
+        *reinterpret_cast<uint32_t*>(gT + (n0 + 2 * q) * GS + 2 * rp) = (v0[q] & 0xffffu) | (v1[q] << 16);
+        *reinterpret_cast<uint32_t*>(gT + (n0 + 2 * q + 1) * GS + 2 * rp) = (v0[q] >> 16) | (v1[q] & 0xffff0000u);
       }
     }
     __syncthreads();
     // gradient window of this lane: rows 8g .. 8g+15 of channel m (taps cut 8 of them)
-    const u32x4 w0 = *reinterpret_cast<const u32x4*>(gT + m * GS + 8 * g);
-    const u32x4 w1 = *reinterpret_cast<const u32x4*>(gT + m * GS + 8 * g + 8);
-    const uint32_t W[8] = {w0[0], w0[1], w0[2], w0[3], w1[0], w1[1], w1[2], w1[3]};
+    uint32_t W[8];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const u32x2 v = *reinterpret_cast<const u32x2*>(gT + m * GS + 8 * g + 4 * h);
+      W[2 * h] = v[0];
+      W[2 * h + 1] = v[1];
+    }
     // input fragments: column c = 16 ct + r16, rows 8g .. 8g+7
     bf16x8 bx[CT];
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
-      bx[ct] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(xT + (16 * ct + r16) * XS + 8 * g));
+    for (int ct = 0; ct < CT; ++ct) {
+      const uint16_t* src = xT + (16 * ct + r16) * XS + 8 * g;
+      const u32x2 lo = *reinterpret_cast<const u32x2*>(src);
+      const u32x2 hi = *reinterpret_cast<const u32x2*>(src + 4);
+      const u32x4 v = {lo[0], lo[1], hi[0], hi[1]};
+      bx[ct] = __builtin_bit_cast(bf16x8, v);
+    }
 #pragma unroll
     for (int tap = 0; tap < KT; ++tap) {
       // rows 8g + j - tap + 8 of the window, j = 0..7: elements e .. e+7 with e = 8 - tap
