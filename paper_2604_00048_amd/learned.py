@@ -166,7 +166,7 @@ def train(device, steps: int = 400, batch_size: int = 4096, lr: float = 1e-3, se
     return L
 
 
-def evaluate(L: Learned, device, n_series: int = 262144, chunk: int = 16384, seed: int = 2604004806,
+def evaluate(L: Learned, device, n_series: int = 262144, chunk: int = 65536, seed: int = 2604004806,
              Ls: LearnedScalar | None = None, clouds: float = 0.0):
     """Held-out RMSE (data units) and throughput of the learned and the plain forms on fresh series
     (and of the learned shared weight, if given)."""
