@@ -73,21 +73,55 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
   }
   const float bv = (MODE != 2 && bias) ? bias[n] : 0.f;
 
+  // input window of a tile: rows t0-4 .. t0+67 (zero outside 0..T-1) in 16-byte
+  // chunks, PRE per lane (the launcher uses NTH lanes per group); with PF the
+  // next tile's window is fetched into registers while the current one is
+  // computed. Only the 64-in, 64-out layers gain from it: the 64-lane groups
+  // would need 36 more registers, and the thin-input layers lose occupancy
+  // for a window too small to matter.
+  constexpr int NTH = NOUT == 64 ? 256 : 64;
+  constexpr bool PF = CIN == 64 && NOUT == 64;
+  constexpr int CH = CIN / 8;
+  constexpr int PRE = (ROWS * CH + NTH - 1) / NTH;
+  u32x4 pre[PF ? PRE : 1];
+  auto fetch = [&](int64_t tx) {
+    if constexpr (!PF) return;
+    const int64_t pp = tx / ntiles;
+    const int tt0 = (int)(tx - pp * ntiles) * TM;
+    const uint16_t* ip = in + pp * (int64_t)T * CIN;
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) {
+      const int i = (int)threadIdx.x + q * NTH;
+      pre[q] = u32x4{0u, 0u, 0u, 0u};
+      if (i < ROWS * CH) {
+        const int t = tt0 - HALO + i / CH;
+        if (t >= 0 && t < T) pre[q] = *reinterpret_cast<const u32x4*>(ip + (int64_t)t * CIN + 8 * (i % CH));
+      }
+    }
+  };
+  if (PF && (int64_t)blockIdx.x < total) fetch(blockIdx.x);
+
   for (int64_t tix = blockIdx.x; tix < total; tix += gridDim.x) {
   const int64_t p = tix / ntiles;
   const int t0 = (int)(tix - p * ntiles) * TM;
-  const uint16_t* inp = in + p * (int64_t)T * CIN;
   __syncthreads();  // the previous tile's window and output tile are no longer read
-  // input window rows t0-4 .. t0+67 (zero outside 0..T-1), 16-byte chunks
-  constexpr int CH = CIN / 8;
-  for (int i = threadIdx.x; i < ROWS * CH; i += blockDim.x) {
-    const int r = i / CH, c8 = i % CH;
-    const int t = t0 - HALO + r;
-    u32x4 v = {0u, 0u, 0u, 0u};
-    if (t >= 0 && t < T) v = *reinterpret_cast<const u32x4*>(inp + (int64_t)t * CIN + 8 * c8);
-    *reinterpret_cast<u32x4*>(win + r * RS + 8 * c8) = v;
+  if constexpr (PF) {
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) {
+      const int i = (int)threadIdx.x + q * NTH;
+      if (i < ROWS * CH) *reinterpret_cast<u32x4*>(win + (i / CH) * RS + 8 * (i % CH)) = pre[q];
+    }
+  } else {
+    const uint16_t* inp = in + p * (int64_t)T * CIN;
+    for (int i = threadIdx.x; i < ROWS * CH; i += blockDim.x) {
+      const int t = t0 - HALO + i / CH;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (t >= 0 && t < T) v = *reinterpret_cast<const u32x4*>(inp + (int64_t)t * CIN + 8 * (i % CH));
+      *reinterpret_cast<u32x4*>(win + (i / CH) * RS + 8 * (i % CH)) = v;
+    }
   }
   __syncthreads();
+  if (PF && tix + gridDim.x < total) fetch(tix + gridDim.x);
 
   f32x4 acc[4];
 #pragma unroll
