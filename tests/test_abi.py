@@ -34,6 +34,12 @@ def test_every_declared_symbol_is_exported():
         assert hasattr(L, n), n
         assert n in net.NET_SIGNATURES, f"binding lacks {n}"
     net.lib()  # every signature binds
+    from paper_2604_00048_amd import tf
+    for n in _declared("whs_tf.h"):
+        assert hasattr(L, n), n
+        assert n in tf.TF_SIGNATURES, f"binding lacks {n}"
+    assert set(tf.TF_SIGNATURES) == set(_declared("whs_tf.h"))
+    tf.lib()
 
 
 def test_status_strings_and_version():
@@ -202,3 +208,30 @@ def test_network_entry_points_validate_arguments():
     assert L.whs_net_adam(FAKE, FAKE, FAKE, FAKE, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1   # step >= 1
     assert L.whs_net_scalar_head_fwd(FAKE, 10, 5.0, -1.0, FAKE, None) == -1                    # hi > lo
     assert L.whs_net_scalar_head_bwd(FAKE, FAKE, 0, -1.0, 5.0, FAKE, None) == -1               # P >= 1
+
+
+def test_transformer_entry_points_validate_arguments():
+    from paper_2604_00048_amd import tf
+    L = tf.lib()
+    # unsupported widths and modes, missing operands, empty inputs, small workspaces
+    assert L.whs_tf_linear(FAKE, 0, 96, FAKE, None, 64, 0, None, None, FAKE, 100, None) == -1     # K
+    assert L.whs_tf_linear(FAKE, 0, 64, FAKE, None, 64, 5, None, None, FAKE, 100, None) == -1     # mode
+    assert L.whs_tf_linear(FAKE, 1, 64, FAKE, None, 64, 4, None, None, FAKE, 100, None) == -1     # mask
+    assert L.whs_tf_linear(FAKE, 0, 64, FAKE, None, 64, 2, None, None, FAKE, 100, None) == -1     # residual
+    assert L.whs_tf_linear(FAKE, 1, 192, FAKE, None, 64, 3, None, None, FAKE, 100, None) == -2    # no such product
+    assert L.whs_tf_linear(FAKE, 0, 64, FAKE, None, 64, 0, None, None, FAKE, 0, None) == 0        # empty
+    n = L.whs_tf_wgrad_workspace_bytes(192, 64, 5)
+    assert n == 5 * (192 * 64 + 192) * 4
+    assert L.whs_tf_wgrad(FAKE, 0, 192, FAKE, 64, 100, FAKE, FAKE, n - 1, 5, None) == -4
+    assert L.whs_tf_wgrad(FAKE, 0, 192, FAKE, 192, 100, FAKE, FAKE, n, 5, None) == -1              # K
+    assert L.whs_tf_attn_fwd(FAKE, 4, 0, FAKE, FAKE, None) == -1                                   # T >= 1
+    assert L.whs_tf_attn_fwd(FAKE, 4, 4097, FAKE, FAKE, None) == -1
+    assert L.whs_tf_attn_bwd(FAKE, FAKE, None, FAKE, 4, 10, FAKE, None) == -1
+    assert L.whs_tf_head_fwd(FAKE, 4, 2, FAKE, 64, 2, -6.0, 10.0, FAKE, FAKE, FAKE, FAKE, None) == -1   # T <= d
+    assert L.whs_tf_head_fwd(FAKE, 4, 9, FAKE, 64, 2, 10.0, -6.0, FAKE, FAKE, FAKE, FAKE, None) == -1   # hi > lo
+    assert L.whs_tf_embed(FAKE, FAKE, 4, 9, 16, 64, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == -1    # C <= 15
+    assert L.whs_tf_embed_bwd(FAKE, FAKE, 10, 17, FAKE, FAKE, 1 << 20, 4, None) == -1                  # F <= 16
+    assert L.whs_tf_ln_bwd(FAKE, FAKE, FAKE, FAKE, FAKE, 10, FAKE, FAKE, FAKE, 0, 4, None) == -4
+    assert L.whs_tf_head_bwd(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 4, 9, 64, 2, -6.0, 10.0, FAKE, FAKE, FAKE, 0, 4,
+                             None) == -4
+    assert L.whs_tf_cast(FAKE, 0, 64, FAKE, None, None) == -1
