@@ -236,12 +236,42 @@ def bench_learned(args):
     }
 
 
+def bench_transformer(args):
+    """Heteroscedastic transformer weights vs one learned weight on irregular
+    multi-band series through the uneven-date smoother: held-out RMSE and time."""
+    import torch
+    from paper_2604_00048_amd import learned_tf
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    het, hom, s_step = learned_tf.train(dev, steps=args.train_steps, batch_size=4096, lr=args.lr, T=args.acq,
+                                        C=args.bands, clouds=args.clouds,
+                                        log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    ev = learned_tf.evaluate(het, hom, dev, n_series=args.eval_series, T=args.acq, C=args.bands, clouds=args.clouds)
+    return {
+        "metric": f"held-out RMSE (transformer per-acquisition lambda vs one learned lambda), T={args.acq} uneven "
+                  f"dates, C={args.bands}, d=2",
+        "value": ev["rmse_hetero_transformer"], "unit": "reflectance RMSE", "n_gpus": 1, "steps": args.train_steps,
+        "warmup": 0, "ms_per_step": s_step * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
+        "config": {"workload": f"heteroscedastic vs homoscedastic smoothing of irregular series: 2-layer "
+                               f"transformer (width 64, 2 heads, sinusoidal date encoding, BF16 MFMA products) "
+                               f"trained {args.train_steps} steps of 4096 series sharing {args.acq} acquisition "
+                               f"dates, {args.bands} bands, through the uneven-date smoother; evaluated on "
+                               f"{args.eval_series} fresh series",
+                   "train_steps": args.train_steps, "lr": args.lr, "clouds": args.clouds},
+        "heldout": ev,
+        "train_seconds": t_train,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="hetero", choices=["hetero", "multiband", "uneven", "learned"])
+    ap.add_argument("--workload", default="hetero", choices=["hetero", "multiband", "uneven", "learned", "transformer"])
     ap.add_argument("--P", type=int, default=None)
     ap.add_argument("--T", type=int, default=3288)
     ap.add_argument("--d", type=int, default=2, help="difference order of the heteroscedastic workload")
@@ -253,7 +283,10 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--clouds", type=float, default=0.0,
                     help="learned workload: fraction of acquisitions cloud-contaminated and kept as observed")
-    ap.add_argument("--eval-series", type=int, default=262144)
+    ap.add_argument("--eval-series", type=int, default=None,
+                    help="learned workloads: fresh series scored (262144, or 32768 for the transformer)")
+    ap.add_argument("--acq", type=int, default=280, help="transformer workload: acquisitions per series")
+    ap.add_argument("--bands", type=int, default=4, help="transformer workload: spectral bands")
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -288,7 +321,12 @@ def main():
         print(json.dumps(bench_uneven(args)), flush=True)
         return
     if args.workload == "learned":
+        args.eval_series = args.eval_series or 262144
         print(json.dumps(bench_learned(args)), flush=True)
+        return
+    if args.workload == "transformer":
+        args.eval_series = args.eval_series or 32768
+        print(json.dumps(bench_transformer(args)), flush=True)
         return
     args.P = args.P or 65536
     print(json.dumps(bench_hetero(args)), flush=True)

@@ -252,6 +252,37 @@ def uneven_groups(n_series=100_000, seed=SEED_BASE + 4, lengths=(365, 730, 1461,
     return groups
 
 
+def acquisition_days(T: int, gen, device, revisit: int = 5, n_days: int = 3288) -> torch.Tensor:
+    """``T`` distinct acquisition days (float64, ascending) drawn from a nominal
+    ``revisit``-day pass calendar over ``n_days`` days: the dates one patch of
+    pixels shares (the paper's series have median length 280 over about nine
+    years, Sec. IV-A)."""
+    passes = n_days // revisit
+    if not 1 <= T <= passes:
+        raise ValueError(f"T must be in [1, {passes}]")
+    r = torch.rand(passes, generator=gen, device=device, dtype=torch.float64)
+    pick = torch.sort(torch.argsort(r)[:T]).values
+    return (pick * revisit + 1).to(torch.float64)
+
+
+def irregular_sits(P: int, T: int, C: int, seed: int, device, chunk: int = 0, p_valid=(0.3, 0.8)):
+    """Irregular multi-band series: ``P`` pixels sharing ``T`` acquisition days,
+    double-logistic bands sampled at those days with N(0, 0.02) noise, and a
+    per-pixel validity mask ``w ~ Bernoulli(p)``, ``p ~ U[p_valid]`` (the
+    masks a cloud detector provides).  Returns ``(days, Batch)``, the batch in
+    natural layout with ``x`` zero where ``w`` is 0."""
+    gen = _gen(seed * 1_000_003 + chunk, device)
+    days = acquisition_days(T, gen, device)
+    x_day, clean_day = phenology(P, 3288, C, gen, device)
+    idx = days.long()
+    x = x_day[:, idx, :].contiguous()
+    clean = clean_day[:, idx, :].contiguous()
+    del x_day, clean_day
+    pv = _u(gen, (P,), p_valid[0], p_valid[1], device)
+    w = bernoulli_mask(P, T, pv, gen, device)
+    return days, Batch(_finish(x, w), w, None, 2, clean)
+
+
 def cloud_contaminate(x: torch.Tensor, w: torch.Tensor, frac: float, gen):
     """Cloud-contaminated acquisitions kept as observed (their mask withheld):
     each observed sample is cloudy with probability ``frac``; a cloudy value is
