@@ -8,10 +8,9 @@
 // of A and column l%16 of B with K entries 8*(l/16) .. +7; accumulator lane l
 // holds rows 4*(l/16) .. +3 of column l%16.
 //
-// Attention is FP32 vector arithmetic: one lane per query (forward, query
-// gradient) or per key (key and value gradients), the other side staged in
-// LDS 256 rows at a time and read as wave-wide broadcasts, so any T fits in a
-// fixed 32 KB and the results match an exact softmax to FP32 rounding.
+// Attention runs on the same matrix cores, 16 queries (or keys) per
+// wavefront, the other side staged in LDS 128 rows at a time so any T fits in
+// a fixed amount of LDS.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -30,7 +29,6 @@ constexpr int NH = 2;        // heads
 constexpr int DH = 32;       // head width
 constexpr int QKV = 3 * E;   // q, k, v columns
 constexpr float LN_EPS = 1e-5f;
-constexpr int KC = 256;      // attention rows staged per chunk
 constexpr int MAXT = 4096;
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -50,34 +48,6 @@ __device__ __forceinline__ float sum16(float v) {
   v += __shfl_xor(v, 2);
   v += __shfl_xor(v, 1);
   return v;
-}
-
-// 32 bfloat16 (one head row, 64 bytes) -> FP32
-__device__ __forceinline__ void load_row32(const uint16_t* src, float* dst) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const u32x4 v = *reinterpret_cast<const u32x4*>(src + 8 * c);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      dst[8 * c + 2 * q] = lo_bf(v[q]);
-      dst[8 * c + 2 * q + 1] = hi_bf(v[q]);
-    }
-  }
-}
-__device__ __forceinline__ void store_row32(uint16_t* dst, const float* v, float scale) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    u32x4 o;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) o[q] = pack2(v[8 * c + 2 * q] * scale, v[8 * c + 2 * q + 1] * scale);
-    *reinterpret_cast<u32x4*>(dst + 8 * c) = o;
-  }
-}
-__device__ __forceinline__ float dot32(const float* a, const float* b) {
-  float s = 0.f;
-#pragma unroll
-  for (int d = 0; d < DH; ++d) s += a[d] * b[d];
-  return s;
 }
 
 // ---------------------------------------------------------------------------
@@ -430,184 +400,306 @@ __global__ __launch_bounds__(256) void k_wgrad(const void* __restrict__ dy, int 
 }
 
 // ---------------------------------------------------------------------------
-// attention
+// attention on the matrix cores
+//
+// Per (series, head) the scores of 16 keys x 16 queries are one MFMA with the
+// key rows as A and the query rows as B (K = the 32 head channels), so a lane
+// ends up holding 4 keys of one query.  Two such blocks (32 keys) give each
+// lane 8 keys, {4g..4g+3} and {16+4g..16+4g+3} with g = lane/16, which is
+// exactly the K slice a lane supplies as the B operand of the next MFMA: the
+// probabilities (or score gradients) go from accumulator to operand without
+// leaving the lane, and the other operand reads the same keys from a
+// transposed copy in LDS.  Probabilities and score gradients are split into a
+// bfloat16 high part and a bfloat16 remainder (two MFMAs), which keeps about 16
+// significant bits; scores and value products are exact bfloat16 products
+// summed in FP32.
 // ---------------------------------------------------------------------------
 constexpr float kScale = 0.17677669529663688f;  // 1/sqrt(32)
+constexpr int ACH = 128;        // rows staged per chunk
+constexpr int RSD = DH + 8;     // row-major LDS stride (bf16): 80 bytes
+constexpr int TSD = ACH + 8;    // transposed LDS stride (bf16): 272 bytes
 
-// stage rows r0 .. r0+nr-1 of one head's 32 columns (column offset col) into LDS
-__device__ __forceinline__ void stage_rows(uint16_t* dst, const uint16_t* base, int64_t stride, int col, int r0,
-                                           int nr) {
-  for (int i = threadIdx.x; i < nr * 4; i += blockDim.x) {
+__device__ __forceinline__ u32x4 ld16(const uint16_t* p) { return *reinterpret_cast<const u32x4*>(p); }
+
+// rows r0 .. r0+ACH-1 (zero from nr on) of one head's 32 columns, row-major, stride RSD
+__device__ __forceinline__ void stage_r(uint16_t* dst, const uint16_t* base, int64_t stride, int col, int r0, int nr) {
+  for (int i = threadIdx.x; i < ACH * 4; i += blockDim.x) {
     const int r = i >> 2, c = i & 3;
-    *reinterpret_cast<u32x4*>(dst + r * DH + 8 * c) =
-        *reinterpret_cast<const u32x4*>(base + (int64_t)(r0 + r) * stride + col + 8 * c);
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (r < nr) v = ld16(base + (int64_t)(r0 + r) * stride + col + 8 * c);
+    *reinterpret_cast<u32x4*>(dst + r * RSD + 8 * c) = v;
   }
 }
+// the same rows transposed, dst[channel][row], stride TSD; pairs of rows per 4-byte store
+__device__ __forceinline__ void stage_t(uint16_t* dst, const uint16_t* base, int64_t stride, int col, int r0, int nr) {
+  for (int i = threadIdx.x; i < (ACH / 2) * 4; i += blockDim.x) {
+    const int j = i >> 2, c = i & 3;
+    u32x4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
+    if (2 * j < nr) v0 = ld16(base + (int64_t)(r0 + 2 * j) * stride + col + 8 * c);
+    if (2 * j + 1 < nr) v1 = ld16(base + (int64_t)(r0 + 2 * j + 1) * stride + col + 8 * c);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      *reinterpret_cast<uint32_t*>(dst + (8 * c + 2 * q) * TSD + 2 * j) = (v0[q] & 0xffffu) | (v1[q] << 16);
+      *reinterpret_cast<uint32_t*>(dst + (8 * c + 2 * q + 1) * TSD + 2 * j) = (v0[q] >> 16) | (v1[q] & 0xffff0000u);
+    }
+  }
+}
+// A operand from a transposed copy: channel row ch, the 8 rows {b+4g..b+4g+3, b+16+4g..+3}
+__device__ __forceinline__ bf16x8 ld_t(const uint16_t* t, int ch, int b, int g) {
+  const u32x2 x = *reinterpret_cast<const u32x2*>(t + ch * TSD + b + 4 * g);
+  const u32x2 y = *reinterpret_cast<const u32x2*>(t + ch * TSD + b + 16 + 4 * g);
+  return __builtin_bit_cast(bf16x8, u32x4{x[0], x[1], y[0], y[1]});
+}
+__device__ __forceinline__ bf16x8 ld_r(const uint16_t* r, int row, int g) {
+  return __builtin_bit_cast(bf16x8, ld16(r + row * RSD + 8 * g));
+}
+// 8 FP32 values -> bfloat16 high parts and bfloat16 remainders
+__device__ __forceinline__ void split8(const float* v, bf16x8& hi, bf16x8& lo) {
+  u32x4 h, l;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint16_t a = f2bf(v[2 * q]), b = f2bf(v[2 * q + 1]);
+    h[q] = (uint32_t)a | ((uint32_t)b << 16);
+    l[q] = pack2(v[2 * q] - lo_bf(a), v[2 * q + 1] - lo_bf(b));
+  }
+  hi = __builtin_bit_cast(bf16x8, h);
+  lo = __builtin_bit_cast(bf16x8, l);
+}
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ float max_g(float v) {
+  v = fmaxf(v, __shfl_xor(v, 16));
+  return fmaxf(v, __shfl_xor(v, 32));
+}
+__device__ __forceinline__ float sum_g(float v) {
+  v += __shfl_xor(v, 16);
+  return v + __shfl_xor(v, 32);
+}
+// lane's 4 accumulator rows 4g+r, r = 0..3, as 4 bfloat16 (8 bytes) at dst
+__device__ __forceinline__ void st4(uint16_t* dst, f32x4 v, float s) {
+  *reinterpret_cast<u32x2*>(dst) = u32x2{pack2(v[0] * s, v[1] * s), pack2(v[2] * s, v[3] * s)};
+}
 
-// grid (P*NH, query blocks); lane = query; online softmax over 16-key groups
-__global__ __launch_bounds__(512) void k_attn_fwd(const uint16_t* __restrict__ qkv, int T, uint16_t* __restrict__ o,
+// Forward.  Workgroup: 4 waves x 16 queries (blockIdx.y selects 64 queries);
+// keys and transposed values staged ACH rows at a time; online softmax per
+// 32-key block.  Lane (g, c) owns query c of its wave; row sums stay per lane
+// until the end.
+__global__ __launch_bounds__(256) void k_attn_fwd(const uint16_t* __restrict__ qkv, int T, uint16_t* __restrict__ o,
                                                   float* __restrict__ lse) {
-  __shared__ __attribute__((aligned(16))) uint16_t ks[KC * DH];
-  __shared__ __attribute__((aligned(16))) uint16_t vs[KC * DH];
+  __shared__ __attribute__((aligned(16))) uint16_t ks[ACH * RSD];
+  __shared__ __attribute__((aligned(16))) uint16_t vt[DH * TSD];
   const int64_t p = blockIdx.x / NH;
   const int hd = blockIdx.x % NH;
   const uint16_t* base = qkv + p * (int64_t)T * QKV;
-  const int qi = blockIdx.y * blockDim.x + threadIdx.x;
-  const bool act = qi < T;
-  float qf[DH], acc[DH];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int qi = blockIdx.y * 64 + wave * 16 + c;
+  bf16x8 qb = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
+  if (qi < T) qb = __builtin_bit_cast(bf16x8, ld16(base + (int64_t)qi * QKV + DH * hd + 8 * g));
   float mx = -INFINITY, l = 0.f;
+  f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+  const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+  for (int c0 = 0; c0 < T; c0 += ACH) {
+    const int nk = T - c0 < ACH ? T - c0 : ACH;
+    __syncthreads();
+    stage_r(ks, base, QKV, E + DH * hd, c0, nk);
+    stage_t(vt, base, QKV, 2 * E + DH * hd, c0, nk);
+    __syncthreads();
+    for (int kb = 0; kb < nk; kb += 32) {
+      const f32x4 sa = mfma(ld_r(ks, kb + c, g), qb, z4);
+      const f32x4 sb = mfma(ld_r(ks, kb + 16 + c, g), qb, z4);
+      float sv[8];
 #pragma unroll
-  for (int d = 0; d < DH; ++d) acc[d] = 0.f;
-  if (act) {
-    load_row32(base + (int64_t)qi * QKV + DH * hd, qf);
+      for (int r = 0; r < 4; ++r) {
+        sv[r] = kb + 4 * g + r < nk ? sa[r] * kScale : -INFINITY;
+        sv[4 + r] = kb + 16 + 4 * g + r < nk ? sb[r] * kScale : -INFINITY;
+      }
+      float bm = sv[0];
 #pragma unroll
-    for (int d = 0; d < DH; ++d) qf[d] *= kScale;
+      for (int i = 1; i < 8; ++i) bm = fmaxf(bm, sv[i]);
+      bm = max_g(bm);
+      const float mn = fmaxf(mx, bm);
+      const float cf = __expf(mx - mn);
+      mx = mn;
+      float pv[8], ps = 0.f;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        pv[i] = __expf(sv[i] - mx);
+        ps += pv[i];
+      }
+      l = l * cf + ps;
+      bf16x8 ph, pl;
+      split8(pv, ph, pl);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const bf16x8 a = ld_t(vt, 16 * t + c, kb, g);
+        acc[t] = mfma(a, pl, acc[t] * cf);
+        acc[t] = mfma(a, ph, acc[t]);
+      }
+    }
   }
-  for (int c0 = 0; c0 < T; c0 += KC) {
-    const int nk = T - c0 < KC ? T - c0 : KC;
+  l = sum_g(l);
+  if (qi >= T) return;
+  uint16_t* dst = o + (p * T + qi) * (int64_t)E + DH * hd;
+  st4(dst + 4 * g, acc[0], 1.f / l);
+  st4(dst + 16 + 4 * g, acc[1], 1.f / l);
+  if (g == 0) lse[(p * NH + hd) * (int64_t)T + qi] = mx + logf(l);
+}
+
+// Query gradient: dq = scale sum_k p (dp - delta) k.  Lane (g, c) owns query c
+// of its wave; keys, values (row-major) and keys (transposed) staged per chunk.
+__global__ __launch_bounds__(256) void k_attn_bwd_q(const uint16_t* __restrict__ qkv, const uint16_t* __restrict__ o,
+                                                    const uint16_t* __restrict__ go, const float* __restrict__ lse,
+                                                    int T, uint16_t* __restrict__ dqkv) {
+  __shared__ __attribute__((aligned(16))) uint16_t ks[ACH * RSD];
+  __shared__ __attribute__((aligned(16))) uint16_t vs[ACH * RSD];
+  __shared__ __attribute__((aligned(16))) uint16_t kt[DH * TSD];
+  const int64_t p = blockIdx.x / NH;
+  const int hd = blockIdx.x % NH;
+  const uint16_t* base = qkv + p * (int64_t)T * QKV;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int qi = blockIdx.y * 64 + wave * 16 + c;
+  const bool act = qi < T;
+  u32x4 qv = {0u, 0u, 0u, 0u}, dv = {0u, 0u, 0u, 0u}, ov = {0u, 0u, 0u, 0u};
+  float L = 0.f;
+  if (act) {
+    qv = ld16(base + (int64_t)qi * QKV + DH * hd + 8 * g);
+    dv = ld16(go + (p * T + qi) * (int64_t)E + DH * hd + 8 * g);
+    ov = ld16(o + (p * T + qi) * (int64_t)E + DH * hd + 8 * g);
+    L = lse[(p * NH + hd) * (int64_t)T + qi];
+  }
+  float dl = 0.f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dl += lo_bf(dv[q]) * lo_bf(ov[q]) + hi_bf(dv[q]) * hi_bf(ov[q]);
+  dl = sum_g(dl);
+  const bf16x8 qb = __builtin_bit_cast(bf16x8, qv), db = __builtin_bit_cast(bf16x8, dv);
+  const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc[2] = {z4, z4};
+  for (int c0 = 0; c0 < T; c0 += ACH) {
+    const int nk = T - c0 < ACH ? T - c0 : ACH;
     __syncthreads();
-    stage_rows(ks, base, QKV, E + DH * hd, c0, nk);
-    stage_rows(vs, base, QKV, 2 * E + DH * hd, c0, nk);
+    stage_r(ks, base, QKV, E + DH * hd, c0, nk);
+    stage_r(vs, base, QKV, 2 * E + DH * hd, c0, nk);
+    stage_t(kt, base, QKV, E + DH * hd, c0, nk);
     __syncthreads();
-    if (!act) continue;
-    for (int j0 = 0; j0 < nk; j0 += 16) {
-      float sc[16];
-      float bm = -INFINITY;
+    for (int kb = 0; kb < nk; kb += 32) {
+      const f32x4 sa = mfma(ld_r(ks, kb + c, g), qb, z4);
+      const f32x4 sb = mfma(ld_r(ks, kb + 16 + c, g), qb, z4);
+      const f32x4 pa = mfma(ld_r(vs, kb + c, g), db, z4);
+      const f32x4 pb = mfma(ld_r(vs, kb + 16 + c, g), db, z4);
+      float ds[8];
 #pragma unroll
-      for (int jj = 0; jj < 16; ++jj) {
-        sc[jj] = -INFINITY;
-        if (j0 + jj < nk) {
-          float kf[DH];
-          load_row32(ks + (j0 + jj) * DH, kf);
-          sc[jj] = dot32(qf, kf);
-        }
-        bm = fmaxf(bm, sc[jj]);
+      for (int r = 0; r < 4; ++r) {
+        const float ea = kb + 4 * g + r < nk ? __expf(sa[r] * kScale - L) : 0.f;
+        const float eb = kb + 16 + 4 * g + r < nk ? __expf(sb[r] * kScale - L) : 0.f;
+        ds[r] = ea * (pa[r] - dl);
+        ds[4 + r] = eb * (pb[r] - dl);
       }
-      if (bm > mx) {
-        const float cf = __expf(mx - bm);
-        l *= cf;
+      bf16x8 hh, ll;
+      split8(ds, hh, ll);
 #pragma unroll
-        for (int d = 0; d < DH; ++d) acc[d] *= cf;
-        mx = bm;
-      }
-#pragma unroll
-      for (int jj = 0; jj < 16; ++jj) {
-        if (j0 + jj < nk) {
-          const float pj = __expf(sc[jj] - mx);
-          l += pj;
-          float vf[DH];
-          load_row32(vs + (j0 + jj) * DH, vf);
-#pragma unroll
-          for (int d = 0; d < DH; ++d) acc[d] += pj * vf[d];
-        }
+      for (int t = 0; t < 2; ++t) {
+        const bf16x8 a = ld_t(kt, 16 * t + c, kb, g);
+        acc[t] = mfma(a, ll, acc[t]);
+        acc[t] = mfma(a, hh, acc[t]);
       }
     }
   }
   if (!act) return;
-  store_row32(o + (p * T + qi) * (int64_t)E + DH * hd, acc, 1.f / l);
-  lse[(p * NH + hd) * (int64_t)T + qi] = mx + logf(l);
+  uint16_t* dst = dqkv + (p * T + qi) * (int64_t)QKV + DH * hd;
+  st4(dst + 4 * g, acc[0], kScale);
+  st4(dst + 16 + 4 * g, acc[1], kScale);
 }
 
-// key and value gradients: lane = key; queries (q, do, lse, delta) staged per chunk
-__global__ __launch_bounds__(512) void k_attn_bwd_kv(const uint16_t* __restrict__ qkv, const uint16_t* __restrict__ o,
+// Key and value gradients: dv = sum_q p do, dk = scale sum_q p (dp - delta) q.
+// Lane (g, c) owns key c of its wave; queries (row-major and transposed), output
+// gradients (both), log-sum-exps and deltas staged per chunk.
+__global__ __launch_bounds__(256) void k_attn_bwd_kv(const uint16_t* __restrict__ qkv, const uint16_t* __restrict__ o,
                                                      const uint16_t* __restrict__ go, const float* __restrict__ lse,
                                                      int T, uint16_t* __restrict__ dqkv) {
-  __shared__ __attribute__((aligned(16))) uint16_t qs[KC * DH];
-  __shared__ __attribute__((aligned(16))) uint16_t dos[KC * DH];
-  __shared__ float ls[KC], dl[KC];
+  __shared__ __attribute__((aligned(16))) uint16_t qs[ACH * RSD];
+  __shared__ __attribute__((aligned(16))) uint16_t dos[ACH * RSD];
+  __shared__ __attribute__((aligned(16))) uint16_t qt[DH * TSD];
+  __shared__ __attribute__((aligned(16))) uint16_t dt[DH * TSD];
+  __shared__ float ls[ACH], dl[ACH];
   const int64_t p = blockIdx.x / NH;
   const int hd = blockIdx.x % NH;
   const uint16_t* base = qkv + p * (int64_t)T * QKV;
   const uint16_t* gob = go + p * (int64_t)T * E;
   const uint16_t* ob = o + p * (int64_t)T * E;
   const float* lb = lse + (p * NH + hd) * (int64_t)T;
-  const int kj = blockIdx.y * blockDim.x + threadIdx.x;
-  const bool act = kj < T;
-  float kf[DH], vf[DH], dk[DH], dv[DH];
-#pragma unroll
-  for (int d = 0; d < DH; ++d) {
-    dk[d] = 0.f;
-    dv[d] = 0.f;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int kj = blockIdx.y * 64 + wave * 16 + c;
+  u32x4 kv = {0u, 0u, 0u, 0u}, vv = {0u, 0u, 0u, 0u};
+  if (kj < T) {
+    kv = ld16(base + (int64_t)kj * QKV + E + DH * hd + 8 * g);
+    vv = ld16(base + (int64_t)kj * QKV + 2 * E + DH * hd + 8 * g);
   }
-  if (act) {
-    load_row32(base + (int64_t)kj * QKV + E + DH * hd, kf);
-    load_row32(base + (int64_t)kj * QKV + 2 * E + DH * hd, vf);
-  }
-  for (int c0 = 0; c0 < T; c0 += KC) {
-    const int nq = T - c0 < KC ? T - c0 : KC;
+  const bf16x8 kb8 = __builtin_bit_cast(bf16x8, kv), vb8 = __builtin_bit_cast(bf16x8, vv);
+  const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+  f32x4 adv[2] = {z4, z4}, adk[2] = {z4, z4};
+  for (int c0 = 0; c0 < T; c0 += ACH) {
+    const int nq = T - c0 < ACH ? T - c0 : ACH;
     __syncthreads();
-    stage_rows(qs, base, QKV, DH * hd, c0, nq);
-    stage_rows(dos, gob, E, DH * hd, c0, nq);
-    for (int r = threadIdx.x; r < nq; r += blockDim.x) {
-      float a[DH], b[DH];
-      load_row32(gob + (int64_t)(c0 + r) * E + DH * hd, a);
-      load_row32(ob + (int64_t)(c0 + r) * E + DH * hd, b);
-      dl[r] = dot32(a, b);
-      ls[r] = lb[c0 + r];
+    stage_r(qs, base, QKV, DH * hd, c0, nq);
+    stage_r(dos, gob, E, DH * hd, c0, nq);
+    stage_t(qt, base, QKV, DH * hd, c0, nq);
+    stage_t(dt, gob, E, DH * hd, c0, nq);
+    for (int r = threadIdx.x; r < ACH; r += blockDim.x) {
+      float d = 0.f, L = INFINITY;   // rows past the end: p = 0
+      if (r < nq) {
+        const uint16_t* a = gob + (int64_t)(c0 + r) * E + DH * hd;
+        const uint16_t* b = ob + (int64_t)(c0 + r) * E + DH * hd;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const u32x4 x = ld16(a + 8 * cc), y = ld16(b + 8 * cc);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) d += lo_bf(x[q]) * lo_bf(y[q]) + hi_bf(x[q]) * hi_bf(y[q]);
+        }
+        L = lb[c0 + r];
+      }
+      dl[r] = d;
+      ls[r] = L;
     }
     __syncthreads();
-    if (!act) continue;
-    for (int r = 0; r < nq; ++r) {
-      float qf[DH], df[DH];
-      load_row32(qs + r * DH, qf);
-      load_row32(dos + r * DH, df);
-      const float pr = __expf(dot32(qf, kf) * kScale - ls[r]);
-      const float ds = pr * (dot32(df, vf) - dl[r]);
+    for (int qb = 0; qb < nq; qb += 32) {
+      // scores and output-gradient products, queries as rows: lane holds queries 4g+r of each half
+      const f32x4 sa = mfma(ld_r(qs, qb + c, g), kb8, z4);
+      const f32x4 sb = mfma(ld_r(qs, qb + 16 + c, g), kb8, z4);
+      const f32x4 pa = mfma(ld_r(dos, qb + c, g), vb8, z4);
+      const f32x4 pb = mfma(ld_r(dos, qb + 16 + c, g), vb8, z4);
+      float pr[8], ds[8];
 #pragma unroll
-      for (int d = 0; d < DH; ++d) {
-        dv[d] += pr * df[d];
-        dk[d] += ds * qf[d];
+      for (int r = 0; r < 4; ++r) {
+        const int ia = qb + 4 * g + r, ib = qb + 16 + 4 * g + r;
+        pr[r] = __expf(sa[r] * kScale - ls[ia]);
+        pr[4 + r] = __expf(sb[r] * kScale - ls[ib]);
+        ds[r] = pr[r] * (pa[r] - dl[ia]);
+        ds[4 + r] = pr[4 + r] * (pb[r] - dl[ib]);
+      }
+      bf16x8 ph, pl, hh, ll;
+      split8(pr, ph, pl);
+      split8(ds, hh, ll);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const bf16x8 a = ld_t(dt, 16 * t + c, qb, g);
+        adv[t] = mfma(a, pl, adv[t]);
+        adv[t] = mfma(a, ph, adv[t]);
+        const bf16x8 b = ld_t(qt, 16 * t + c, qb, g);
+        adk[t] = mfma(b, ll, adk[t]);
+        adk[t] = mfma(b, hh, adk[t]);
       }
     }
   }
-  if (!act) return;
-  uint16_t* dst = dqkv + (p * T + kj) * (int64_t)QKV;
-  store_row32(dst + E + DH * hd, dk, kScale);
-  store_row32(dst + 2 * E + DH * hd, dv, 1.f);
-}
-
-// query gradients: lane = query; keys and values staged per chunk
-__global__ __launch_bounds__(512) void k_attn_bwd_q(const uint16_t* __restrict__ qkv, const uint16_t* __restrict__ o,
-                                                    const uint16_t* __restrict__ go, const float* __restrict__ lse,
-                                                    int T, uint16_t* __restrict__ dqkv) {
-  __shared__ __attribute__((aligned(16))) uint16_t ks[KC * DH];
-  __shared__ __attribute__((aligned(16))) uint16_t vs[KC * DH];
-  const int64_t p = blockIdx.x / NH;
-  const int hd = blockIdx.x % NH;
-  const uint16_t* base = qkv + p * (int64_t)T * QKV;
-  const int qi = blockIdx.y * blockDim.x + threadIdx.x;
-  const bool act = qi < T;
-  float qf[DH], df[DH], dq[DH];
-  float L = 0.f, delta = 0.f;
-#pragma unroll
-  for (int d = 0; d < DH; ++d) dq[d] = 0.f;
-  if (act) {
-    load_row32(base + (int64_t)qi * QKV + DH * hd, qf);
-    load_row32(go + (p * T + qi) * (int64_t)E + DH * hd, df);
-    float of[DH];
-    load_row32(o + (p * T + qi) * (int64_t)E + DH * hd, of);
-    delta = dot32(df, of);
-    L = lse[(p * NH + hd) * (int64_t)T + qi];
-  }
-  for (int c0 = 0; c0 < T; c0 += KC) {
-    const int nk = T - c0 < KC ? T - c0 : KC;
-    __syncthreads();
-    stage_rows(ks, base, QKV, E + DH * hd, c0, nk);
-    stage_rows(vs, base, QKV, 2 * E + DH * hd, c0, nk);
-    __syncthreads();
-    if (!act) continue;
-    for (int j = 0; j < nk; ++j) {
-      float kf[DH], vf[DH];
-      load_row32(ks + j * DH, kf);
-      load_row32(vs + j * DH, vf);
-      const float pr = __expf(dot32(qf, kf) * kScale - L);
-      const float ds = pr * (dot32(df, vf) - delta);
-#pragma unroll
-      for (int d = 0; d < DH; ++d) dq[d] += ds * kf[d];
-    }
-  }
-  if (!act) return;
-  store_row32(dqkv + (p * T + qi) * (int64_t)QKV + DH * hd, dq, kScale);
+  if (kj >= T) return;
+  uint16_t* dst = dqkv + (p * T + kj) * (int64_t)QKV + DH * hd;
+  st4(dst + E + 4 * g, adk[0], kScale);
+  st4(dst + E + 16 + 4 * g, adk[1], kScale);
+  st4(dst + 2 * E + 4 * g, adv[0], 1.f);
+  st4(dst + 2 * E + 16 + 4 * g, adv[1], 1.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -733,12 +825,6 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 constexpr int64_t kLinBlocks = 2048;
 hipStream_t hs(void* s) { return static_cast<hipStream_t>(s); }
 bool okn(int n) { return n == 64 || n == 128 || n == 192; }
-// query (or key) blocks of an attention launch: at most 512 lanes each
-void attn_shape(int T, unsigned& nb, unsigned& threads) {
-  nb = (unsigned)((T + 511) / 512);
-  const int per = (T + (int)nb - 1) / (int)nb;
-  threads = (unsigned)(64 * ((per + 63) / 64));
-}
 }  // namespace
 
 extern "C" {
@@ -822,9 +908,8 @@ int whs_tf_wgrad(const void* dy, int dy_f32, int N, const uint16_t* x, int K, in
 int whs_tf_attn_fwd(const uint16_t* qkv, int64_t P, int T, uint16_t* o, float* lse, void* stream) {
   if (!qkv || !o || !lse || P < 0 || T < 1 || T > MAXT) return -1;
   if (P == 0) return 0;
-  unsigned nb, th;
-  attn_shape(T, nb, th);
-  hipLaunchKernelGGL(k_attn_fwd, dim3((unsigned)(P * NH), nb), dim3(th), 0, hs(stream), qkv, T, o, lse);
+  const dim3 grid((unsigned)(P * NH), (unsigned)((T + 63) / 64));
+  hipLaunchKernelGGL(k_attn_fwd, grid, dim3(256), 0, hs(stream), qkv, T, o, lse);
   return st(hipGetLastError());
 }
 
@@ -832,10 +917,9 @@ int whs_tf_attn_bwd(const uint16_t* qkv, const uint16_t* o, const uint16_t* go, 
                     int T, uint16_t* dqkv, void* stream) {
   if (!qkv || !o || !go || !lse || !dqkv || P < 0 || T < 1 || T > MAXT) return -1;
   if (P == 0) return 0;
-  unsigned nb, th;
-  attn_shape(T, nb, th);
-  hipLaunchKernelGGL(k_attn_bwd_kv, dim3((unsigned)(P * NH), nb), dim3(th), 0, hs(stream), qkv, o, go, lse, T, dqkv);
-  hipLaunchKernelGGL(k_attn_bwd_q, dim3((unsigned)(P * NH), nb), dim3(th), 0, hs(stream), qkv, o, go, lse, T, dqkv);
+  const dim3 grid((unsigned)(P * NH), (unsigned)((T + 63) / 64));
+  hipLaunchKernelGGL(k_attn_bwd_kv, grid, dim3(256), 0, hs(stream), qkv, o, go, lse, T, dqkv);
+  hipLaunchKernelGGL(k_attn_bwd_q, grid, dim3(256), 0, hs(stream), qkv, o, go, lse, T, dqkv);
   return st(hipGetLastError());
 }
 
