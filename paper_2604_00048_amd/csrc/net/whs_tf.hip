@@ -99,12 +99,22 @@ __global__ void k_cast(const float* __restrict__ w, int N, int K, uint16_t* __re
   if (out_t) out_t[k * N + n] = b;
 }
 
-__global__ void k_reduce(const float* __restrict__ part, int nparts, int len, float* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= len) return;
+// out[i] = sum_w part[w][i]: 64 outputs per workgroup, 16 lanes per output each
+// summing every 16th partial, then the 16 sums added in a fixed order
+__global__ __launch_bounds__(1024) void k_reduce(const float* __restrict__ part, int nparts, int len,
+                                                 float* __restrict__ out) {
+  __shared__ float red[16][64];
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63), sl = threadIdx.x >> 6;
   float s = 0.f;
-  for (int w = 0; w < nparts; ++w) s += part[(int64_t)w * len + i];
-  out[i] = s;
+  if (col < len)
+    for (int w = sl; w < nparts; w += 16) s += part[(int64_t)w * len + col];
+  red[sl][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (sl == 0 && col < len) {
+    float t = 0.f;
+    for (int k = 0; k < 16; ++k) t += red[k][threadIdx.x];
+    out[col] = t;
+  }
 }
 
 // dWe[e][f] = sum_m gh[m][e] feats[m][f], dbe[e] = sum_m gh[m][e]; lane = channel,
@@ -270,23 +280,51 @@ __global__ __launch_bounds__(256) void k_lin(const void* __restrict__ xin, const
         const u32x4 a = *reinterpret_cast<const u32x4*>(xs + (16 * mm + r16) * RS + 32 * s + 8 * g);
         acc[mm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), wb[s], acc[mm], 0, 0, 0);
       }
+    if constexpr (MODE == 2 || MODE == 3) {
+      // FP32 out: 16 lanes write 64 contiguous bytes of a row
 #pragma unroll
-    for (int mm = 0; mm < 4; ++mm)
+      for (int mm = 0; mm < 4; ++mm)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t row = r0 + 16 * mm + 4 * g + j;
-        if (row >= M) continue;
-        const int64_t o = row * N + n;
-        const float v = acc[mm][j] + bv;
-        if constexpr (MODE == 0) static_cast<uint16_t*>(out)[o] = f2bf(v);
-        if constexpr (MODE == 1) static_cast<uint16_t*>(out)[o] = f2bf(v > 0.f ? v : 0.f);
-        if constexpr (MODE == 2) static_cast<float*>(out)[o] = res[o] + v;
-        if constexpr (MODE == 3) static_cast<float*>(out)[o] = acc[mm][j];
-        if constexpr (MODE == 4) {
-          const uint16_t mk = mask[o];
-          static_cast<uint16_t*>(out)[o] = ((mk & 0x8000u) == 0u && (mk & 0x7fffu) != 0u) ? f2bf(acc[mm][j]) : 0;
+        for (int j = 0; j < 4; ++j) {
+          const int64_t row = r0 + 16 * mm + 4 * g + j;
+          if (row >= M) continue;
+          const int64_t o = row * N + n;
+          if constexpr (MODE == 2) static_cast<float*>(out)[o] = res[o] + acc[mm][j] + bv;
+          else static_cast<float*>(out)[o] = acc[mm][j];
         }
+    } else {
+      // bfloat16 out: the 64 x 64 tile goes through LDS (reusing the input
+      // tile) and leaves as 16-byte row pieces; the ReLU mask is applied there
+      constexpr int OS = 64 + 8;
+      static_assert(64 * OS <= 64 * RS, "output tile fits in the input tile");
+      __syncthreads();
+#pragma unroll
+      for (int mm = 0; mm < 4; ++mm)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float v = MODE == 4 ? acc[mm][j] : acc[mm][j] + bv;
+          xs[(16 * mm + 4 * g + j) * OS + wave * 16 + r16] = f2bf(MODE == 1 && v < 0.f ? 0.f : v);
+        }
+      __syncthreads();
+      uint16_t* ob = static_cast<uint16_t*>(out);
+      const int n0 = blockIdx.y * 64;
+      for (int i = threadIdx.x; i < 64 * 8; i += 256) {
+        const int r = i >> 3, c8 = i & 7;
+        const int64_t row = r0 + r;
+        if (row >= M) continue;
+        u32x4 v = *reinterpret_cast<const u32x4*>(xs + r * OS + 8 * c8);
+        if constexpr (MODE == 4) {
+          const u32x4 mv = *reinterpret_cast<const u32x4*>(mask + row * N + n0 + 8 * c8);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const uint32_t lo = (mv[q] & 0x7fffu) != 0u && !(mv[q] & 0x8000u) ? 0x0000ffffu : 0u;
+            const uint32_t hi = ((mv[q] >> 16) & 0x7fffu) != 0u && !(mv[q] & 0x80000000u) ? 0xffff0000u : 0u;
+            v[q] &= (lo | hi);
+          }
+        }
+        *reinterpret_cast<u32x4*>(ob + row * N + n0 + 8 * c8) = v;
       }
+    }
   }
 }
 
@@ -860,7 +898,7 @@ int whs_tf_ln_bwd(const float* ga, const float* h, const float* mean, const floa
   if (!ga || !h || !mean || !rstd || !gb || !gh || !dgb || !ws || M < 1 || parts < 1) return -1;
   if (ws_bytes < whs_tf_ln_bwd_workspace_bytes(parts)) return -4;
   hipLaunchKernelGGL(k_ln_bwd, dim3(parts), dim3(256), 0, hs(stream), ga, h, mean, rstd, gb, M, gh, ws);
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(2 * E), 0, hs(stream), ws, parts, 2 * E, dgb);
+  hipLaunchKernelGGL(k_reduce, dim3(nblk(2 * E, 64)), dim3(1024), 0, hs(stream), ws, parts, 2 * E, dgb);
   return st(hipGetLastError());
 }
 
@@ -901,7 +939,7 @@ int whs_tf_wgrad(const void* dy, int dy_f32, int N, const uint16_t* x, int K, in
   else if (dy_f32) hipLaunchKernelGGL((k_wgrad<128, true>), grid, dim3(256), 0, hs(stream), dy, N, x, M, ws);
   else hipLaunchKernelGGL((k_wgrad<128, false>), grid, dim3(256), 0, hs(stream), dy, N, x, M, ws);
   const int len = N * K + N;
-  hipLaunchKernelGGL(k_reduce, dim3(nblk(len, 256)), dim3(256), 0, hs(stream), ws, parts, len, dwb);
+  hipLaunchKernelGGL(k_reduce, dim3(nblk(len, 64)), dim3(1024), 0, hs(stream), ws, parts, len, dwb);
   return st(hipGetLastError());
 }
 
@@ -946,7 +984,7 @@ int whs_tf_head_bwd(const float* h, const float* s, const float* mean, const flo
   if (ws_bytes < whs_tf_head_bwd_workspace_bytes(parts)) return -4;
   hipLaunchKernelGGL(k_head_bwd, dim3(parts), dim3(256), 0, hs(stream), h, s, mean, rstd, hp, glam, P, T, S, d, lo,
                      hi, gh, ws);
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, hs(stream), ws, parts, 3 * E + 1, dhp);
+  hipLaunchKernelGGL(k_reduce, dim3(nblk(3 * E + 1, 64)), dim3(1024), 0, hs(stream), ws, parts, 3 * E + 1, dhp);
   return st(hipGetLastError());
 }
 
@@ -960,7 +998,7 @@ int whs_tf_embed_bwd(const float* gh, const float* feats, int64_t M, int F, floa
   if (ws_bytes < whs_tf_embed_bwd_workspace_bytes(F, parts)) return -4;
   hipLaunchKernelGGL(k_embed_bwd, dim3(parts), dim3(256), 0, hs(stream), gh, feats, M, F, ws);
   const int len = E * F + E;
-  hipLaunchKernelGGL(k_reduce, dim3(nblk(len, 256)), dim3(256), 0, hs(stream), ws, parts, len, dweb);
+  hipLaunchKernelGGL(k_reduce, dim3(nblk(len, 64)), dim3(1024), 0, hs(stream), ws, parts, len, dweb);
   return st(hipGetLastError());
 }
 
