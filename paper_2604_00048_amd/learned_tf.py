@@ -168,7 +168,7 @@ def evaluate(het: Hetero, hom: Homo, device, n_series: int = 16384, chunk: int =
     sse_h = sse_o = cl_h = cl_o = 0.0
     n = 0
     t_h = 0.0
-    lam_lo = []
+    lam_sd = []
     for i, p0 in enumerate(range(0, n_series, chunk)):
         P = min(chunk, n_series - p0)
         b = make_batch(P, seed, i, device, T=T, C=C, clouds=clouds)
@@ -185,7 +185,7 @@ def evaluate(het: Hetero, hom: Homo, device, n_series: int = 16384, chunk: int =
             cl_h += _sse(z_h, b.x_clean, b.hold)
             cl_o += _sse(z_o, b.x_clean, b.hold)
         n += b.n_hold
-        lam_lo.append(torch.log10(lam.double()).std().item())
+        lam_sd.append(torch.log10(lam.double()).std().item())
     out = {
         "n_series": n_series,
         "acquisitions": T,
@@ -195,7 +195,7 @@ def evaluate(het: Hetero, hom: Homo, device, n_series: int = 16384, chunk: int =
         "rmse_homo_scalar": math.sqrt(sse_o / n),
         "gain": 1.0 - math.sqrt(sse_h / n) / math.sqrt(sse_o / n),
         "log10_lambda_homo": hom.log10_lambda(),
-        "sd_log10_lambda_hetero": sum(lam_lo) / len(lam_lo),
+        "sd_log10_lambda_hetero": sum(lam_sd) / len(lam_sd),
         "series_per_s_hetero": n_series / t_h,
     }
     if clouds > 0:
