@@ -342,3 +342,23 @@ def gpu_cache(model: tf.TransformerNet, p):
     cache["af"] = cache["xhatf"] * p["gf"] + p["bf"]
     assert M == P * T
     return cache
+
+
+def test_bfloat16_rounding_is_nearest_even():
+    # exact ties at several exponents and signs, their neighbours, values that
+    # round up into the next binade and past the largest finite value, plus
+    # random values over many binades (FP32 denormals are not used anywhere)
+    one = np.float32(1.0)
+    e = [np.float32(2.0 ** k) for k in (-20, -3, 0, 5, 40)]
+    ties = []
+    for s in e:
+        for m in range(8):
+            t = s * (one + np.float32((2 * m + 1) * 2.0 ** -8))      # halfway between two bfloat16 values
+            ties += [t, -t, np.nextafter(t, np.float32(0)), np.nextafter(t, np.float32(np.inf))]
+    special = [np.float32(1.9999999), np.float32(3.3e38), np.float32(3.4e38), np.float32(0.0), np.float32(-0.0)]
+    rnd = (rng.normal(size=4000) * 10.0 ** rng.uniform(-30, 30, size=4000)).astype(np.float32)
+    v = np.concatenate([np.array(ties + special, dtype=np.float32), rnd])
+    out = torch.empty((1, v.size), dtype=torch.int16, device=dev)
+    tf.cast(f32(v), 1, v.size, out)
+    got = out.cpu().view(torch.bfloat16).to(torch.float64).numpy()[0]
+    np.testing.assert_array_equal(got, N.bf16_round(v.astype(np.float64)))
