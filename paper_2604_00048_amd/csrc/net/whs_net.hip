@@ -25,13 +25,8 @@ constexpr int KT = 9;    // taps
 constexpr int HALO = 4;  // zero padding on each side
 constexpr int TM = 64;   // output time rows per tile
 
-// float -> bfloat16 bits, round to nearest even (NaN kept quiet)
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __builtin_bit_cast(uint32_t, f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// float -> bfloat16 bits, round to nearest even (gfx950 converts in one instruction)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
 
 // ---------------------------------------------------------------------------
