@@ -58,31 +58,35 @@ __global__ void k_pe(const double* __restrict__ times, int T, float* __restrict_
   pe[t * E + 2 * j + 1] = (float)cos(a);
 }
 
-// one lane per (token, channel)
-__global__ void k_embed(const float* __restrict__ x, const uint8_t* __restrict__ w, int64_t P, int T, int C, int S,
-                        const float* __restrict__ mean, const float* __restrict__ inv_sd,
-                        const float* __restrict__ pe, const float* __restrict__ web, float* __restrict__ feats,
-                        float* __restrict__ h) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P * T * E) return;
-  const int64_t m = i / E;
-  const int e = (int)(i - m * E);
+// 16 lanes per token, 4 channels per lane (one 16-byte store each)
+__global__ __launch_bounds__(256) void k_embed(const float* __restrict__ x, const uint8_t* __restrict__ w, int64_t P,
+                                               int T, int C, int S, const float* __restrict__ mean,
+                                               const float* __restrict__ inv_sd, const float* __restrict__ pe,
+                                               const float* __restrict__ web, float* __restrict__ feats,
+                                               float* __restrict__ h) {
+  const int64_t m = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int q = threadIdx.x & 15;
+  if (m >= P * T) return;
   const int64_t p = m / T;
   const int t = (int)(m - p * T);
   const int64_t b = p / S;
   const int s = (int)(p - b * S);
   const int F = C + 1;
   const bool obs = w[(b * T + t) * S + s] != 0;
-  float acc = web[E * F + e] + pe[t * E + e];
+  f32x4 acc = *reinterpret_cast<const f32x4*>(pe + t * E + 4 * q);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] += web[E * F + 4 * q + j];
   for (int c = 0; c < C; ++c) {
     const float xs = obs ? (x[((b * T + t) * C + c) * S + s] - mean[c]) * inv_sd[c] : 0.f;
-    acc += web[e * F + c] * xs;
-    if (e == 0) feats[m * F + c] = xs;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] += web[(4 * q + j) * F + c] * xs;
+    if (q == 0) feats[m * F + c] = xs;
   }
   const float wf = obs ? 1.f : 0.f;
-  acc += web[e * F + C] * wf;
-  if (e == 0) feats[m * F + C] = wf;
-  h[m * E + e] = acc;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] += web[(4 * q + j) * F + C] * wf;
+  if (q == 0) feats[m * F + C] = wf;
+  *reinterpret_cast<f32x4*>(h + m * E + 4 * q) = acc;
 }
 
 __global__ void k_cast(const float* __restrict__ w, int N, int K, uint16_t* __restrict__ out,
@@ -122,12 +126,21 @@ __global__ __launch_bounds__(256) void k_embed_bwd(const float* __restrict__ gh,
   float acc[16], db = 0.f;
 #pragma unroll
   for (int f = 0; f < 16; ++f) acc[f] = 0.f;
-  for (int64_t m = (int64_t)blockIdx.x * 4 + slot; m < M; m += (int64_t)gridDim.x * 4) {
-    const float g = gh[m * E + e];
-    db += g;
+  // four tokens per iteration, their loads issued together
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  for (int64_t m0 = (int64_t)blockIdx.x * 4 + slot; m0 < M; m0 += 4 * stride) {
+    float g[4];
 #pragma unroll
-    for (int f = 0; f < 16; ++f)
-      if (f < F) acc[f] += g * feats[m * F + f];
+    for (int u = 0; u < 4; ++u) g[u] = m0 + u * stride < M ? gh[(m0 + u * stride) * E + e] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t m = m0 + u * stride;
+      if (m >= M) break;
+      db += g[u];
+#pragma unroll
+      for (int f = 0; f < 16; ++f)
+        if (f < F) acc[f] += g[u] * feats[m * F + f];
+    }
   }
 #pragma unroll
   for (int f = 0; f < 16; ++f)
@@ -874,7 +887,7 @@ int whs_tf_embed(const float* x, const uint8_t* w, int64_t P, int T, int C, int 
   if (!x || !w || !mean || !inv_sd || !pe || !web || !feats || !h || P < 0 || T < 1 || C < 1 || C > 15 || S < 1)
     return -1;
   if (P == 0) return 0;
-  hipLaunchKernelGGL(k_embed, dim3(nblk(P * T * E, 256)), dim3(256), 0, hs(stream), x, w, P, T, C, S, mean, inv_sd,
+  hipLaunchKernelGGL(k_embed, dim3(nblk(P * T * 16, 256)), dim3(256), 0, hs(stream), x, w, P, T, C, S, mean, inv_sd,
                      pe, web, feats, h);
   return st(hipGetLastError());
 }
