@@ -463,6 +463,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const void* __restrict__ dy, int 
 // ---------------------------------------------------------------------------
 constexpr float kScale = 0.17677669529663688f;  // 1/sqrt(32)
 constexpr int ACH = 128;        // rows staged per chunk
+constexpr int AWG = 8;          // wavefronts per attention workgroup (16 rows each)
 constexpr int RSD = DH + 8;     // row-major LDS stride (bf16): 80 bytes
 constexpr int TSD = ACH + 8;    // transposed LDS stride (bf16): 272 bytes
 
@@ -528,11 +529,11 @@ __device__ __forceinline__ void st4(uint16_t* dst, f32x4 v, float s) {
   *reinterpret_cast<u32x2*>(dst) = u32x2{pack2(v[0] * s, v[1] * s), pack2(v[2] * s, v[3] * s)};
 }
 
-// Forward.  Workgroup: 4 waves x 16 queries (blockIdx.y selects 64 queries);
+// Forward.  Workgroup: AWG waves x 16 queries (blockIdx.y selects 16 AWG queries);
 // keys and transposed values staged ACH rows at a time; online softmax per
 // 32-key block.  Lane (g, c) owns query c of its wave; row sums stay per lane
 // until the end.
-__global__ __launch_bounds__(256) void k_attn_fwd(const uint16_t* __restrict__ qkv, int T, uint16_t* __restrict__ o,
+__global__ __launch_bounds__(64 * AWG) void k_attn_fwd(const uint16_t* __restrict__ qkv, int T, uint16_t* __restrict__ o,
                                                   float* __restrict__ lse) {
   __shared__ __attribute__((aligned(16))) uint16_t ks[ACH * RSD];
   __shared__ __attribute__((aligned(16))) uint16_t vt[DH * TSD];
@@ -541,7 +542,7 @@ __global__ __launch_bounds__(256) void k_attn_fwd(const uint16_t* __restrict__ q
   const uint16_t* base = qkv + p * (int64_t)T * QKV;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c = lane & 15;
-  const int qi = blockIdx.y * 64 + wave * 16 + c;
+  const int qi = blockIdx.y * (16 * AWG) + wave * 16 + c;
   bf16x8 qb = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
   if (qi < T) qb = __builtin_bit_cast(bf16x8, ld16(base + (int64_t)qi * QKV + DH * hd + 8 * g));
   float mx = -INFINITY, l = 0.f;
@@ -596,7 +597,7 @@ __global__ __launch_bounds__(256) void k_attn_fwd(const uint16_t* __restrict__ q
 
 // Query gradient: dq = scale sum_k p (dp - delta) k.  Lane (g, c) owns query c
 // of its wave; keys, values (row-major) and keys (transposed) staged per chunk.
-__global__ __launch_bounds__(256) void k_attn_bwd_q(const uint16_t* __restrict__ qkv, const uint16_t* __restrict__ o,
+__global__ __launch_bounds__(64 * AWG) void k_attn_bwd_q(const uint16_t* __restrict__ qkv, const uint16_t* __restrict__ o,
                                                     const uint16_t* __restrict__ go, const float* __restrict__ lse,
                                                     int T, uint16_t* __restrict__ dqkv) {
   __shared__ __attribute__((aligned(16))) uint16_t ks[ACH * RSD];
@@ -607,7 +608,7 @@ __global__ __launch_bounds__(256) void k_attn_bwd_q(const uint16_t* __restrict__
   const uint16_t* base = qkv + p * (int64_t)T * QKV;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c = lane & 15;
-  const int qi = blockIdx.y * 64 + wave * 16 + c;
+  const int qi = blockIdx.y * (16 * AWG) + wave * 16 + c;
   const bool act = qi < T;
   u32x4 qv = {0u, 0u, 0u, 0u}, dv = {0u, 0u, 0u, 0u}, ov = {0u, 0u, 0u, 0u};
   float L = 0.f;
@@ -663,7 +664,7 @@ __global__ __launch_bounds__(256) void k_attn_bwd_q(const uint16_t* __restrict__
 // Key and value gradients: dv = sum_q p do, dk = scale sum_q p (dp - delta) q.
 // Lane (g, c) owns key c of its wave; queries (row-major and transposed), output
 // gradients (both), log-sum-exps and deltas staged per chunk.
-__global__ __launch_bounds__(256) void k_attn_bwd_kv(const uint16_t* __restrict__ qkv, const uint16_t* __restrict__ o,
+__global__ __launch_bounds__(64 * AWG) void k_attn_bwd_kv(const uint16_t* __restrict__ qkv, const uint16_t* __restrict__ o,
                                                      const uint16_t* __restrict__ go, const float* __restrict__ lse,
                                                      int T, uint16_t* __restrict__ dqkv) {
   __shared__ __attribute__((aligned(16))) uint16_t qs[ACH * RSD];
@@ -679,7 +680,7 @@ __global__ __launch_bounds__(256) void k_attn_bwd_kv(const uint16_t* __restrict_
   const float* lb = lse + (p * NH + hd) * (int64_t)T;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c = lane & 15;
-  const int kj = blockIdx.y * 64 + wave * 16 + c;
+  const int kj = blockIdx.y * (16 * AWG) + wave * 16 + c;
   u32x4 kv = {0u, 0u, 0u, 0u}, vv = {0u, 0u, 0u, 0u};
   if (kj < T) {
     kv = ld16(base + (int64_t)kj * QKV + E + DH * hd + 8 * g);
@@ -955,8 +956,8 @@ int whs_tf_wgrad(const void* dy, int dy_f32, int N, const uint16_t* x, int K, in
 int whs_tf_attn_fwd(const uint16_t* qkv, int64_t P, int T, uint16_t* o, float* lse, void* stream) {
   if (!qkv || !o || !lse || P < 0 || T < 1 || T > MAXT) return -1;
   if (P == 0) return 0;
-  const dim3 grid((unsigned)(P * NH), (unsigned)((T + 63) / 64));
-  hipLaunchKernelGGL(k_attn_fwd, grid, dim3(256), 0, hs(stream), qkv, T, o, lse);
+  const dim3 grid((unsigned)(P * NH), (unsigned)((T + 16 * AWG - 1) / (16 * AWG)));
+  hipLaunchKernelGGL(k_attn_fwd, grid, dim3(64 * AWG), 0, hs(stream), qkv, T, o, lse);
   return st(hipGetLastError());
 }
 
@@ -964,9 +965,9 @@ int whs_tf_attn_bwd(const uint16_t* qkv, const uint16_t* o, const uint16_t* go, 
                     int T, uint16_t* dqkv, void* stream) {
   if (!qkv || !o || !go || !lse || !dqkv || P < 0 || T < 1 || T > MAXT) return -1;
   if (P == 0) return 0;
-  const dim3 grid((unsigned)(P * NH), (unsigned)((T + 63) / 64));
-  hipLaunchKernelGGL(k_attn_bwd_kv, grid, dim3(256), 0, hs(stream), qkv, o, go, lse, T, dqkv);
-  hipLaunchKernelGGL(k_attn_bwd_q, grid, dim3(256), 0, hs(stream), qkv, o, go, lse, T, dqkv);
+  const dim3 grid((unsigned)(P * NH), (unsigned)((T + 16 * AWG - 1) / (16 * AWG)));
+  hipLaunchKernelGGL(k_attn_bwd_kv, grid, dim3(64 * AWG), 0, hs(stream), qkv, o, go, lse, T, dqkv);
+  hipLaunchKernelGGL(k_attn_bwd_q, grid, dim3(64 * AWG), 0, hs(stream), qkv, o, go, lse, T, dqkv);
   return st(hipGetLastError());
 }
 

@@ -52,7 +52,8 @@ TF_SIGNATURES = {
 E, H, DH, FF, NL = 64, 2, 32, 128, 2
 LO, HI = -6.0, 10.0
 BF16 = torch.int16   # bfloat16 bits travel as int16 tensors
-PARTS = 512
+PARTS = 512           # workgroups of the weight-gradient and layer-norm reductions
+PARTS_TOKEN = 2048    # workgroups of the per-token reductions (head, embedding): more in flight
 
 _lib = None
 
@@ -129,13 +130,13 @@ def head_fwd(h, P, T, hp, S, d, lo, hi, s, mean, rstd, lam):
                                _s(h.device)), "whs_tf_head_fwd")
 
 
-def head_bwd(h, s, mean, rstd, hp, glam, P, T, S, d, lo, hi, gh, dhp, ws, parts=PARTS):
+def head_bwd(h, s, mean, rstd, hp, glam, P, T, S, d, lo, hi, gh, dhp, ws, parts=PARTS_TOKEN):
     _chk(lib().whs_tf_head_bwd(_p(h), _p(s), _p(mean), _p(rstd), _p(hp), _p(glam), P, T, S, d, lo, hi, _p(gh),
                                _p(dhp), _p(ws), ws.numel() * ws.element_size(), parts, _s(h.device)),
          "whs_tf_head_bwd")
 
 
-def embed_bwd(gh, feats, M, F, dweb, ws, parts=PARTS):
+def embed_bwd(gh, feats, M, F, dweb, ws, parts=PARTS_TOKEN):
     _chk(lib().whs_tf_embed_bwd(_p(gh), _p(feats), M, F, _p(dweb), _p(ws), ws.numel() * ws.element_size(), parts,
                                 _s(gh.device)), "whs_tf_embed_bwd")
 
@@ -144,11 +145,11 @@ def cast(w, N, K, out, out_t=None):
     _chk(lib().whs_tf_cast(_p(w), N, K, _p(out), _p(out_t), _s(w.device)), "whs_tf_cast")
 
 
-def workspace_bytes(F: int, parts: int = PARTS) -> int:
+def workspace_bytes(F: int) -> int:
     L = lib()
-    return max(int(L.whs_tf_wgrad_workspace_bytes(3 * E, E, parts)), int(L.whs_tf_wgrad_workspace_bytes(E, FF, parts)),
-               int(L.whs_tf_ln_bwd_workspace_bytes(parts)), int(L.whs_tf_head_bwd_workspace_bytes(parts)),
-               int(L.whs_tf_embed_bwd_workspace_bytes(F, parts)))
+    return max(int(L.whs_tf_wgrad_workspace_bytes(3 * E, E, PARTS)), int(L.whs_tf_wgrad_workspace_bytes(E, FF, PARTS)),
+               int(L.whs_tf_ln_bwd_workspace_bytes(PARTS)), int(L.whs_tf_head_bwd_workspace_bytes(PARTS_TOKEN)),
+               int(L.whs_tf_embed_bwd_workspace_bytes(F, PARTS_TOKEN)))
 
 
 # ---------------------------------------------------------------------------
