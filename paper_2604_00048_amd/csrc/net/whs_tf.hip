@@ -492,6 +492,19 @@ __device__ __forceinline__ void stage_t(uint16_t* dst, const uint16_t* base, int
     }
   }
 }
+// transposed copy of an LDS row-major copy (rows past the end are already zero)
+__device__ __forceinline__ void transpose_lds(uint16_t* dst, const uint16_t* src) {
+  for (int i = threadIdx.x; i < (ACH / 2) * 4; i += blockDim.x) {
+    const int j = i >> 2, c = i & 3;
+    const u32x4 v0 = *reinterpret_cast<const u32x4*>(src + (2 * j) * RSD + 8 * c);
+    const u32x4 v1 = *reinterpret_cast<const u32x4*>(src + (2 * j + 1) * RSD + 8 * c);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      *reinterpret_cast<uint32_t*>(dst + (8 * c + 2 * q) * TSD + 2 * j) = (v0[q] & 0xffffu) | (v1[q] << 16);
+      *reinterpret_cast<uint32_t*>(dst + (8 * c + 2 * q + 1) * TSD + 2 * j) = (v0[q] >> 16) | (v1[q] & 0xffff0000u);
+    }
+  }
+}
 // A operand from a transposed copy: channel row ch, the 8 rows {b+4g..b+4g+3, b+16+4g..+3}
 __device__ __forceinline__ bf16x8 ld_t(const uint16_t* t, int ch, int b, int g) {
   const u32x2 x = *reinterpret_cast<const u32x2*>(t + ch * TSD + b + 4 * g);
@@ -630,7 +643,8 @@ __global__ __launch_bounds__(64 * AWG) void k_attn_bwd_q(const uint16_t* __restr
     __syncthreads();
     stage_r(ks, base, QKV, E + DH * hd, c0, nk);
     stage_r(vs, base, QKV, 2 * E + DH * hd, c0, nk);
-    stage_t(kt, base, QKV, E + DH * hd, c0, nk);
+    __syncthreads();
+    transpose_lds(kt, ks);
     __syncthreads();
     for (int kb = 0; kb < nk; kb += 32) {
       const f32x4 sa = mfma(ld_r(ks, kb + c, g), qb, z4);
@@ -694,16 +708,16 @@ __global__ __launch_bounds__(64 * AWG) void k_attn_bwd_kv(const uint16_t* __rest
     __syncthreads();
     stage_r(qs, base, QKV, DH * hd, c0, nq);
     stage_r(dos, gob, E, DH * hd, c0, nq);
-    stage_t(qt, base, QKV, DH * hd, c0, nq);
-    stage_t(dt, gob, E, DH * hd, c0, nq);
+    __syncthreads();
+    transpose_lds(qt, qs);
+    transpose_lds(dt, dos);
     for (int r = threadIdx.x; r < ACH; r += blockDim.x) {
       float d = 0.f, L = INFINITY;   // rows past the end: p = 0
       if (r < nq) {
-        const uint16_t* a = gob + (int64_t)(c0 + r) * E + DH * hd;
         const uint16_t* b = ob + (int64_t)(c0 + r) * E + DH * hd;
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
-          const u32x4 x = ld16(a + 8 * cc), y = ld16(b + 8 * cc);
+          const u32x4 x = *reinterpret_cast<const u32x4*>(dos + r * RSD + 8 * cc), y = ld16(b + 8 * cc);
 #pragma unroll
           for (int q = 0; q < 4; ++q) d += lo_bf(x[q]) * lo_bf(y[q]) + hi_bf(x[q]) * hi_bf(y[q]);
         }
