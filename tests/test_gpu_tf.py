@@ -10,9 +10,9 @@ head value within 1e-2 of the reference's own forward; every parameter
 gradient within 5e-3 of the reference backward run on the activations the GPU
 saved (the wiring of the backward), and within 1e-1 end to end, where
 one-step differences in stored bfloat16 values flip ReLU-mask entries.  Sizes span several
-64-row tiles, 32-token chunks and 256-row attention chunks with ragged tails;
-T = 1 and T = 600 (two query blocks) are the edge cases of the attention
-launch."""
+64-row tiles, 32-token chunks and 128-row attention chunks with ragged tails;
+T = 1, T = 128 and 129 (one staged chunk, and one more row) and T = 600 (five
+128-row blocks of queries or keys) are the edge cases of the attention launch."""
 
 import numpy as np
 import pytest
@@ -170,7 +170,7 @@ def merge(a):
     return a.transpose(0, 2, 1, 3).reshape(P, T, E)
 
 
-@pytest.mark.parametrize("T", [1, 37, 300, 600])
+@pytest.mark.parametrize("T", [1, 37, 128, 129, 300, 600])
 def test_attention_forward_backward(T):
     P = 2
     qkv, (q, k, v) = attn_inputs(P, T)
