@@ -685,7 +685,8 @@ __global__ __launch_bounds__(64 * AWG) void k_attn_bwd_kv(const uint16_t* __rest
   __shared__ __attribute__((aligned(16))) uint16_t dos[ACH * RSD];
   __shared__ __attribute__((aligned(16))) uint16_t qt[DH * TSD];
   __shared__ __attribute__((aligned(16))) uint16_t dt[DH * TSD];
-  __shared__ float ls[ACH], dl[ACH];
+  __shared__ __attribute__((aligned(16))) float ls[ACH];
+  __shared__ __attribute__((aligned(16))) float dl[ACH];
   const int64_t p = blockIdx.x / NH;
   const int hd = blockIdx.x % NH;
   const uint16_t* base = qkv + p * (int64_t)T * QKV;
@@ -733,14 +734,18 @@ __global__ __launch_bounds__(64 * AWG) void k_attn_bwd_kv(const uint16_t* __rest
       const f32x4 sb = mfma(ld_r(qs, qb + 16 + c, g), kb8, z4);
       const f32x4 pa = mfma(ld_r(dos, qb + c, g), vb8, z4);
       const f32x4 pb = mfma(ld_r(dos, qb + 16 + c, g), vb8, z4);
+      // statistics of queries qb+4g..+3 and qb+16+4g..+3: four 16-byte reads
+      const f32x4 la = *reinterpret_cast<const f32x4*>(ls + qb + 4 * g);
+      const f32x4 lb4 = *reinterpret_cast<const f32x4*>(ls + qb + 16 + 4 * g);
+      const f32x4 da = *reinterpret_cast<const f32x4*>(dl + qb + 4 * g);
+      const f32x4 db = *reinterpret_cast<const f32x4*>(dl + qb + 16 + 4 * g);
       float pr[8], ds[8];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int ia = qb + 4 * g + r, ib = qb + 16 + 4 * g + r;
-        pr[r] = __expf(sa[r] * kScale - ls[ia]);
-        pr[4 + r] = __expf(sb[r] * kScale - ls[ib]);
-        ds[r] = pr[r] * (pa[r] - dl[ia]);
-        ds[4 + r] = pr[4 + r] * (pb[r] - dl[ib]);
+        pr[r] = __expf(sa[r] * kScale - la[r]);
+        pr[4 + r] = __expf(sb[r] * kScale - lb4[r]);
+        ds[r] = pr[r] * (pa[r] - da[r]);
+        ds[4 + r] = pr[4 + r] * (pb[r] - db[r]);
       }
       bf16x8 ph, pl, hh, ll;
       split8(pr, ph, pl);
