@@ -14,6 +14,7 @@ times the FP64 CPU oracle on a bounded sample of the same inputs.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import math
@@ -277,6 +278,8 @@ def main():
     ap.add_argument("--d", type=int, default=2, help="difference order of the heteroscedastic workload")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--interleave", type=int, default=64)
+    ap.add_argument("--in-place", action="store_true",
+                    help="interleave 1: read the contiguous layout in place instead of through interleaved copies")
     ap.add_argument("--n-uneven", type=int, default=100000)
     ap.add_argument("--retune", action="store_true")
     ap.add_argument("--train-steps", type=int, default=400)
@@ -365,7 +368,11 @@ def bench_hetero(args):
     gl = torch.empty_like(pk.lam)
     info = torch.empty(P, dtype=torch.int32, device=dev)
     desc = whs.make_desc(P, T, d, 1, S, whs.WHS_F32, whs.WHS_LAMBDA_PER_DIFF)
-    ws = torch.empty(whs.workspace_bytes(desc), dtype=torch.uint8, device=dev)
+    nws = whs.workspace_bytes(desc)
+    if S == 1 and not args.in_place:
+        # series-contiguous: the workspace that runs the interleaved kernels on copies
+        nws = max(nws, int(whs.lib().whs_interleave_workspace_bytes(ctypes.byref(desc))))
+    ws = torch.empty(max(nws, 8), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
     print(f"# inputs generated in {t_gen:.1f}s; workspace {ws.numel() / 1e6:.1f} MB", file=sys.stderr, flush=True)
@@ -426,6 +433,7 @@ def bench_hetero(args):
             "workload": f"heteroscedastic smoother fwd+bwd: P={P} series, T={T} daily steps, d={d}, C=1 band, "
                         "per-difference lambda (log10 GP field), FP32 storage / FP64 arithmetic",
             "P": P, "T": T, "d": d, "C": 1, "storage": "f32", "interleave": S,
+            **({"contiguous_path": "in place" if args.in_place else "interleaved copies"} if S == 1 else {}),
         },
         "roofline": {
             "bound": "hbm",

@@ -87,6 +87,20 @@ int whs_version(void);
  * one stream. */
 size_t whs_workspace_bytes(const whs_desc* desc);
 
+/* Series-contiguous inputs (interleave = 1): bytes of a workspace that also
+ * holds interleaved copies of the call's arrays (x or g, z, grad_x, w, and
+ * lambda / grad_lambda when per difference row) plus the checkpoints of the
+ * interleaved kernels; 0 for interleave != 1, P = 0, P >= 2^31 or T*C >
+ * 65535*64 (then only the in-place kernels apply).  Given at least this
+ * much, whs_solve, whs_backward, whs_solve_coef and whs_backward_coef on
+ * interleave 1 (fused path, factor NULL) copy their inputs into the
+ * interleaved layout with a tiled transpose, run the throughput kernels and
+ * copy the results back: about two more passes over the data, for every order
+ * and band count, and the uneven-date calls then accept interleave 1 too.
+ * With less (but at least whs_workspace_bytes), interleave-1 calls run the
+ * kernels that read the contiguous layout in place. */
+size_t whs_interleave_workspace_bytes(const whs_desc* desc);
+
 /* Bytes of the factor array whs_factor writes: P_pad * (d+1) * T * 8. */
 size_t whs_factor_bytes(const whs_desc* desc);
 
@@ -166,9 +180,10 @@ int whs_gcv(const whs_desc* desc, const uint8_t* w, const void* x, const double*
  * not finite are NaN (every solve that uses them then fails with info > 0).
  * whs_solve_coef / whs_backward_coef are whs_solve / whs_backward (fused
  * path, no factor argument) with Omega = W + D^T Lambda D built from coef.
- * They require interleave a multiple of 64 (WHS_ERR_UNSUPPORTED otherwise)
- * and use the whs_workspace_bytes(desc) workspace.  Return codes, info,
- * aliasing and NaN conventions are those of whs_solve / whs_backward.
+ * They require interleave a multiple of 64, or interleave 1 with a workspace
+ * of at least whs_interleave_workspace_bytes(desc) (WHS_ERR_UNSUPPORTED
+ * otherwise), and use the whs_workspace_bytes(desc) workspace.  Return codes,
+ * info, aliasing and NaN conventions are those of whs_solve / whs_backward.
  */
 int whs_diff_coef(const double* times, int32_t T, int32_t d, double* coef, void* stream);
 int whs_solve_coef(const whs_desc* desc, const double* coef, const uint8_t* w, const void* lambda,

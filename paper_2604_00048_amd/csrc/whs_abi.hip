@@ -38,6 +38,105 @@ whs::LaunchDesc make_launch(const whs_desc* d) {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? WHS_OK : WHS_ERR_HIP; }
 
+// Series-contiguous calls (interleave 1) with a large enough workspace run the
+// interleaved kernels on copies: slots for x (or g), z, grad_x, w, lambda and
+// grad_lambda, then the interleaved kernels' checkpoints.
+size_t up256(size_t n) { return (n + 255) / 256 * 256; }
+
+struct Staged {
+  size_t x, w, lam, ck;
+  size_t total() const { return 3 * x + w + 2 * lam + ck; }
+};
+
+Staged staged_sizes(const whs_desc* d) {
+  const size_t nb = (size_t)((d->n_series + 63) / 64);
+  const size_t e = elem(d);
+  Staged s{};
+  s.x = up256(nb * 64 * (size_t)d->T * (size_t)d->n_rhs * e);
+  s.w = up256(nb * 64 * (size_t)d->T);
+  s.lam = d->lambda_kind == WHS_LAMBDA_PER_DIFF ? up256(nb * 64 * (size_t)(d->T - d->d) * e) : 0;
+  s.ck = whs::checkpoint_bytes(d->n_series, 64, d->T, d->d, d->n_rhs);
+  return s;
+}
+
+bool use_staged(const whs_desc* d, const double* factor, size_t ws_bytes) {
+  // the transposes take rows of up to 65535 x 64 elements (second grid dimension)
+  return d->interleave == 1 && !factor && d->n_series > 0 && d->n_series < ((int64_t)1 << 31) &&
+         (int64_t)d->T * d->n_rhs <= (int64_t)65535 * 64 && ws_bytes >= staged_sizes(d).total();
+}
+
+struct Slots {
+  char *x, *z, *gx, *lam, *glam;
+  uint8_t* w;
+  double* ck;
+};
+
+Slots carve(const Staged& s, void* ws) {
+  char* p = static_cast<char*>(ws);
+  Slots o{};
+  o.x = p;
+  o.z = (p += s.x);
+  o.gx = (p += s.x);
+  o.w = reinterpret_cast<uint8_t*>(p += s.x);
+  o.lam = (p += s.w);
+  o.glam = (p += s.lam);
+  o.ck = reinterpret_cast<double*>(p += s.lam);
+  return o;
+}
+
+hipError_t solve_staged(const whs_desc* d, const double* coef, const uint8_t* w, const void* lambda, const void* x,
+                        void* z, int32_t* info, void* ws, hipStream_t s) {
+  const Slots o = carve(staged_sizes(d), ws);
+  const int64_t P = d->n_series, LX = (int64_t)d->T * d->n_rhs;
+  const int e = (int)elem(d);
+  const bool pd = d->lambda_kind == WHS_LAMBDA_PER_DIFF;
+  hipError_t err = whs::launch_interleave(x, o.x, P, LX, e, true, s);
+  if (err == hipSuccess) err = whs::launch_interleave(w, o.w, P, d->T, 1, true, s);
+  if (err == hipSuccess && pd) err = whs::launch_interleave(lambda, o.lam, P, d->T - d->d, e, true, s);
+  if (err != hipSuccess) return err;
+  whs::LaunchDesc L = make_launch(d);
+  L.S = 64;
+  L.coef = coef;
+  L.w = o.w;
+  L.lam = pd ? static_cast<const void*>(o.lam) : lambda;
+  L.rhs = o.x;
+  L.out = o.z;
+  L.info = info;
+  L.ws = o.ck;
+  err = whs::launch_solve(L, s);
+  if (err != hipSuccess) return err;
+  return whs::launch_interleave(o.z, z, P, LX, e, false, s);
+}
+
+hipError_t backward_staged(const whs_desc* d, const double* coef, const uint8_t* w, const void* lambda, const void* z,
+                           const void* g, void* grad_x, void* grad_lambda, int32_t* info, void* ws, hipStream_t s) {
+  const Slots o = carve(staged_sizes(d), ws);
+  const int64_t P = d->n_series, LX = (int64_t)d->T * d->n_rhs;
+  const int e = (int)elem(d);
+  const bool pd = d->lambda_kind == WHS_LAMBDA_PER_DIFF;
+  hipError_t err = whs::launch_interleave(g, o.x, P, LX, e, true, s);
+  if (err == hipSuccess) err = whs::launch_interleave(z, o.z, P, LX, e, true, s);
+  if (err == hipSuccess) err = whs::launch_interleave(w, o.w, P, d->T, 1, true, s);
+  if (err == hipSuccess && pd) err = whs::launch_interleave(lambda, o.lam, P, d->T - d->d, e, true, s);
+  if (err != hipSuccess) return err;
+  whs::LaunchDesc L = make_launch(d);
+  L.S = 64;
+  L.coef = coef;
+  L.w = o.w;
+  L.lam = pd ? static_cast<const void*>(o.lam) : lambda;
+  L.rhs = o.x;
+  L.zin = o.z;
+  L.out = grad_x ? o.gx : nullptr;
+  L.glam = grad_lambda ? (pd ? static_cast<void*>(o.glam) : grad_lambda) : nullptr;
+  L.info = info;
+  L.ws = o.ck;
+  err = whs::launch_backward(L, s);
+  if (err == hipSuccess && grad_x) err = whs::launch_interleave(o.gx, grad_x, P, LX, e, false, s);
+  if (err == hipSuccess && grad_lambda && pd)
+    err = whs::launch_interleave(o.glam, grad_lambda, P, d->T - d->d, e, false, s);
+  return err;
+}
+
 }  // namespace
 
 extern "C" {
@@ -58,6 +157,12 @@ int whs_version(void) { return 100; }
 size_t whs_workspace_bytes(const whs_desc* desc) {
   if (check_desc(desc) != WHS_OK || desc->n_series == 0) return 0;
   return whs::checkpoint_bytes(desc->n_series, desc->interleave, desc->T, desc->d, desc->n_rhs);
+}
+
+size_t whs_interleave_workspace_bytes(const whs_desc* desc) {
+  if (check_desc(desc) != WHS_OK || desc->n_series == 0 || desc->interleave != 1) return 0;
+  if (desc->n_series >= ((int64_t)1 << 31) || (int64_t)desc->T * desc->n_rhs > (int64_t)65535 * 64) return 0;
+  return staged_sizes(desc).total();
 }
 
 size_t whs_factor_bytes(const whs_desc* desc) {
@@ -93,6 +198,8 @@ int whs_solve(const whs_desc* desc, const uint8_t* w, const void* lambda, const 
       !aligned(info, 4))
     return WHS_ERR_ARG;
   if (!workspace || workspace_bytes < whs_workspace_bytes(desc) || !aligned(workspace, 8)) return WHS_ERR_WORKSPACE;
+  if (use_staged(desc, factor, workspace_bytes))
+    return hip_status(solve_staged(desc, nullptr, w, lambda, x, z, info, workspace, static_cast<hipStream_t>(stream)));
   whs::LaunchDesc L = make_launch(desc);
   L.w = w;
   L.lam = lambda;
@@ -118,6 +225,9 @@ int whs_backward(const whs_desc* desc, const uint8_t* w, const void* lambda, con
     return WHS_ERR_ARG;
   if (!workspace || workspace_bytes < whs_workspace_bytes(desc) || !aligned(workspace, 8)) return WHS_ERR_WORKSPACE;
   if (!grad_x && !grad_lambda && !info) return WHS_OK;
+  if (use_staged(desc, factor, workspace_bytes))
+    return hip_status(backward_staged(desc, nullptr, w, lambda, z, g, grad_x, grad_lambda, info, workspace,
+                                      static_cast<hipStream_t>(stream)));
   whs::LaunchDesc L = make_launch(desc);
   L.w = w;
   L.lam = lambda;
@@ -142,13 +252,15 @@ int whs_solve_coef(const whs_desc* desc, const double* coef, const uint8_t* w, c
                    void* z, int32_t* info, void* workspace, size_t workspace_bytes, void* stream) {
   int st = check_desc(desc);
   if (st != WHS_OK) return st;
-  if (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31)) return WHS_ERR_UNSUPPORTED;
+  const bool stg = use_staged(desc, nullptr, workspace_bytes);
+  if (!stg && (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31))) return WHS_ERR_UNSUPPORTED;
   if (desc->n_series == 0) return WHS_OK;
   if (!coef || !w || !lambda || !x || !z) return WHS_ERR_ARG;
   const size_t e = elem(desc);
   if (!aligned(coef, 8) || !aligned(x, e) || !aligned(z, e) || !aligned(lambda, e) || !aligned(info, 4))
     return WHS_ERR_ARG;
   if (!workspace || workspace_bytes < whs_workspace_bytes(desc) || !aligned(workspace, 8)) return WHS_ERR_WORKSPACE;
+  if (stg) return hip_status(solve_staged(desc, coef, w, lambda, x, z, info, workspace, static_cast<hipStream_t>(stream)));
   whs::LaunchDesc L = make_launch(desc);
   L.coef = coef;
   L.w = w;
@@ -165,7 +277,8 @@ int whs_backward_coef(const whs_desc* desc, const double* coef, const uint8_t* w
                       size_t workspace_bytes, void* stream) {
   int st = check_desc(desc);
   if (st != WHS_OK) return st;
-  if (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31)) return WHS_ERR_UNSUPPORTED;
+  const bool stg = use_staged(desc, nullptr, workspace_bytes);
+  if (!stg && (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31))) return WHS_ERR_UNSUPPORTED;
   if (desc->n_series == 0) return WHS_OK;
   if (!coef || !w || !lambda || !z || !g) return WHS_ERR_ARG;
   const size_t e = elem(desc);
@@ -174,6 +287,9 @@ int whs_backward_coef(const whs_desc* desc, const double* coef, const uint8_t* w
     return WHS_ERR_ARG;
   if (!workspace || workspace_bytes < whs_workspace_bytes(desc) || !aligned(workspace, 8)) return WHS_ERR_WORKSPACE;
   if (!grad_x && !grad_lambda && !info) return WHS_OK;
+  if (stg)
+    return hip_status(backward_staged(desc, coef, w, lambda, z, g, grad_x, grad_lambda, info, workspace,
+                                      static_cast<hipStream_t>(stream)));
   whs::LaunchDesc L = make_launch(desc);
   L.coef = coef;
   L.w = w;

@@ -63,6 +63,7 @@ SIGNATURES = {
     "whs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "whs_version": (ctypes.c_int, []),
     "whs_workspace_bytes": (_SZ, [_DP]),
+    "whs_interleave_workspace_bytes": (_SZ, [_DP]),
     "whs_factor_bytes": (_SZ, [_DP]),
     "whs_factor": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP]),
     "whs_solve": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
@@ -156,12 +157,16 @@ def workspace_bytes(desc: WhsDesc) -> int:
     return int(lib().whs_workspace_bytes(ctypes.byref(desc)))
 
 
-def _workspace(desc: WhsDesc, device, workspace):
+def _workspace(desc: WhsDesc, device, workspace, staged: bool = False):
+    """The caller's workspace (checked), or a new one; ``staged``: large enough for
+    series-contiguous calls to run the interleaved kernels on copies."""
     n = workspace_bytes(desc)
     if workspace is not None:
         if workspace.numel() * workspace.element_size() < n:
             raise ValueError(f"workspace has {workspace.numel() * workspace.element_size()} bytes, needs {n}")
         return workspace, n
+    if staged:
+        n = max(n, int(lib().whs_interleave_workspace_bytes(ctypes.byref(desc))))
     return torch.empty(max(n, 8), dtype=torch.uint8, device=device), n
 
 
@@ -214,8 +219,13 @@ def _check_coef(coef, T, d):
 
 
 def whs_solve(x: torch.Tensor, w: torch.Tensor, lam: torch.Tensor | None, d: int, P: int | None = None,
-              factor=None, z=None, info=None, workspace=None, coef=None):
+              factor=None, z=None, info=None, workspace=None, coef=None, staged: bool = True):
     """``z = Omega^{-1} W x`` per series and band.  Returns ``(z, info)``.
+
+    ``staged``: with interleave 1 and no workspace given, allocate the larger
+    workspace that lets the call run the interleaved kernels on copies
+    (``whs_interleave_workspace_bytes``); ``False`` keeps the kernels that read
+    the contiguous layout in place.
 
     ``coef``: rows of ``D`` on uneven sample times (``whs_diff_coef``); the
     daily grid when ``None``.
@@ -232,7 +242,7 @@ def whs_solve(x: torch.Tensor, w: torch.Tensor, lam: torch.Tensor | None, d: int
         z = torch.empty_like(x)
     if info is None:
         info = torch.empty(P, dtype=torch.int32, device=x.device)
-    ws, n = _workspace(desc, x.device, workspace)
+    ws, n = _workspace(desc, x.device, workspace, staged and factor is None)
     if coef is not None:
         if factor is not None:
             raise ValueError("uneven sample times use the fused path (no factor)")
@@ -249,10 +259,10 @@ def whs_solve(x: torch.Tensor, w: torch.Tensor, lam: torch.Tensor | None, d: int
 def whs_backward(w: torch.Tensor, lam: torch.Tensor | None, z: torch.Tensor, g: torch.Tensor, d: int,
                  P: int | None = None, factor=None, need_x: bool = True, need_lambda: bool = True,
                  grad_x=None, grad_lambda=None, info=None, workspace=None, lambda_kind: int | None = None,
-                 coef=None):
+                 coef=None, staged: bool = True):
     """Adjoint against ``g``: ``grad_x = W Omega^{-1} g``, ``grad_lambda_k = -(D u)_k (D z)_k``.
 
-    Returns ``(grad_x or None, grad_lambda or None, info)``.  ``coef`` as in ``whs_solve``.
+    Returns ``(grad_x or None, grad_lambda or None, info)``.  ``coef`` and ``staged`` as in ``whs_solve``.
     """
     _need_gpu(w, lam, z, g, factor, grad_x, grad_lambda, info, workspace, coef)
     nb, T, C, S, P = _geometry(z, P)
@@ -267,7 +277,7 @@ def whs_backward(w: torch.Tensor, lam: torch.Tensor | None, z: torch.Tensor, g: 
         grad_lambda = torch.empty(shape, dtype=z.dtype, device=z.device)
     if info is None:
         info = torch.empty(P, dtype=torch.int32, device=z.device)
-    ws, n = _workspace(desc, z.device, workspace)
+    ws, n = _workspace(desc, z.device, workspace, staged and factor is None)
     if coef is not None:
         if factor is not None:
             raise ValueError("uneven sample times use the fused path (no factor)")

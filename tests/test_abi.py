@@ -108,6 +108,26 @@ def test_workspace_and_factor_sizes():
     assert whs.lib().whs_factor_bytes(ctypes.byref(desc)) == 128 * 3 * 365 * 8
 
 
+def test_interleave_workspace_size():
+    # series-contiguous calls: slots for x/g, z, grad_x (3 x), w, lambda and
+    # grad_lambda (per difference row), each rounded up to 256 bytes, then the
+    # checkpoints of the same call on interleave 64
+    L = whs.lib()
+    up = lambda n: (n + 255) // 256 * 256   # noqa: E731
+    for P, T, d, C, dt, kind in [(100, 365, 2, 1, 0, 1), (65, 3288, 3, 4, 1, 0), (1, 10, 1, 2, 0, 1)]:
+        desc = whs.make_desc(P, T, d, C, 1, dt, kind)
+        e = 8 if dt == 1 else 4
+        nb = (P + 63) // 64
+        x = up(nb * 64 * T * C * e)
+        lam = up(nb * 64 * (T - d) * e) if kind == 1 else 0
+        ck = whs.workspace_bytes(whs.make_desc(P, T, d, C, 64, dt, kind))
+        n = L.whs_interleave_workspace_bytes(ctypes.byref(desc))
+        assert n == 3 * x + up(nb * 64 * T) + 2 * lam + ck
+        assert n >= whs.workspace_bytes(desc)
+    assert L.whs_interleave_workspace_bytes(ctypes.byref(whs.make_desc(100, 365, 2, 1, 64, 0, 1))) == 0
+    assert L.whs_interleave_workspace_bytes(ctypes.byref(whs.make_desc(0, 365, 2, 1, 1, 0, 1))) == 0
+
+
 def test_backward_validation():
     L = whs.lib()
     desc = whs.make_desc(10, 50, 2, 1, 64, 1, 1)

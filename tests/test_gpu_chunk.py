@@ -29,7 +29,7 @@ CASES = [  # P, T, d, per_diff
 
 def _solve(x, w, lam, d, dtype, P):
     xt, wt, lt = to_device(x, w, lam, 1, dtype)
-    z, info = whs.whs_solve(xt, wt, lt, d, P)
+    z, info = whs.whs_solve(xt, wt, lt, d, P, staged=False)
     torch.cuda.synchronize()
     return xt, wt, lt, z, info
 
@@ -53,7 +53,7 @@ def test_chunk_backward_parity(P, T, d, per_diff, dt):
     g = torch.tensor(np.random.default_rng(P + T).normal(size=x.shape)).to(dtype).double().numpy()
     xt, wt, lt, z, _ = _solve(x, w, lam, d, dtype, P)
     gt = synth.pack_series(torch.tensor(g, dtype=dtype), 1).cuda()
-    gx, gl, info = whs.whs_backward(wt, lt, z, gt, d, P)
+    gx, gl, info = whs.whs_backward(wt, lt, z, gt, d, P, staged=False)
     torch.cuda.synchronize()
     zc = from_device_series(z, P)
     gx = from_device_series(gx, P)
@@ -94,9 +94,9 @@ def test_chunk_in_place_and_deterministic():
     P, T, d = 8, 777, 2
     x, w, lam = random_case(P, T, d, per_diff=True, seed=5)
     xt, wt, lt = to_device(x, w, lam, 1, torch.float64)
-    z1, _ = whs.whs_solve(xt, wt, lt, d, P)
-    z2, _ = whs.whs_solve(xt, wt, lt, d, P)
-    whs.whs_solve(xt, wt, lt, d, P, z=xt)       # z aliases x
+    z1, _ = whs.whs_solve(xt, wt, lt, d, P, staged=False)
+    z2, _ = whs.whs_solve(xt, wt, lt, d, P, staged=False)
+    whs.whs_solve(xt, wt, lt, d, P, z=xt, staged=False)   # z aliases x
     torch.cuda.synchronize()
     assert torch.equal(z1, z2) and torch.equal(z1, xt)
 

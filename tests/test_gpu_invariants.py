@@ -1,6 +1,7 @@
 """Invariants the paper's mathematics fixes, checked on the GPU path itself
 (no oracle values involved), in the interleaved layout and in the contiguous
-one (partition kernel for order <= 2): identity for lambda = 0 with every
+one (run on interleaved copies, and read in place by the partition kernel for
+order <= 2 or the one-lane kernel otherwise): identity for lambda = 0 with every
 sample observed (P1), exact reproduction of polynomials of degree < d (P2),
 O(1/lambda) approach to the least-squares polynomial fit (P3), symmetry and
 time reversal (P4), padding with unobserved samples (P5), linearity and
@@ -17,13 +18,23 @@ from paper_2604_00048_amd import synth, whs
 from tests._cases import from_device_rows, from_device_series, to_device
 
 pytestmark = pytest.mark.gpu
-LAYOUTS = [64, 1]
+# interleaved; series-contiguous run through the interleaved kernels on copies;
+# series-contiguous read in place (partition kernel for one band of order <= 2)
+LAYOUTS = [64, 1, "1-in-place"]
+
+
+def _s(S):
+    return 1 if S == "1-in-place" else S
+
+
+def _st(S):
+    return S != "1-in-place"
 
 
 def solve(x, w, lam, d, S):
     x3 = x[:, :, None] if x.ndim == 2 else x
-    xt, wt, lt = to_device(x3, w, lam, S, torch.float64)
-    z, info = whs.whs_solve(xt, wt, lt, d, x.shape[0])
+    xt, wt, lt = to_device(x3, w, lam, _s(S), torch.float64)
+    z, info = whs.whs_solve(xt, wt, lt, d, x.shape[0], staged=_st(S))
     torch.cuda.synchronize()
     assert (info.cpu().numpy() == 0).all()
     z = from_device_series(z, x.shape[0])
@@ -138,10 +149,10 @@ def test_P11_adjoint_dot_product_and_low_degree_gradient(d, S):
     x = np.where(w != 0, r.normal(size=(P, T)), 0.0)
     a = np.where(w != 0, r.normal(size=(P, T)), 0.0)     # a perturbation of x
     g = r.normal(size=(P, T))
-    xt, wt, lt = to_device(x[:, :, None], w, lam, S, torch.float64)
-    z, _ = whs.whs_solve(xt, wt, lt, d, P)
-    gt = synth.pack_series(torch.tensor(g[:, :, None]), S).cuda()
-    gx, gl, _ = whs.whs_backward(wt, lt, z, gt, d, P)
+    xt, wt, lt = to_device(x[:, :, None], w, lam, _s(S), torch.float64)
+    z, _ = whs.whs_solve(xt, wt, lt, d, P, staged=_st(S))
+    gt = synth.pack_series(torch.tensor(g[:, :, None]), _s(S)).cuda()
+    gx, gl, _ = whs.whs_backward(wt, lt, z, gt, d, P, staged=_st(S))
     gx = from_device_series(gx, P)[:, :, 0]
     # <g, dz/dx a> = <grad_x, a>, with dz/dx a the smoother applied to a
     za = solve(a, w, lam, d, S)
@@ -149,9 +160,9 @@ def test_P11_adjoint_dot_product_and_low_degree_gradient(d, S):
     # data that D annihilates: z = x is a polynomial of degree < d, D z = 0, grad_lambda = 0
     t = np.arange(T) / T
     poly = np.where(w != 0, (0.2 + 0.5 * t) if d >= 2 else 0.2 + 0 * t, 0.0)
-    xp, wp, lp = to_device(poly[:, :, None], w, lam, S, torch.float64)
-    zp, _ = whs.whs_solve(xp, wp, lp, d, P)
-    _, glp, _ = whs.whs_backward(wp, lp, zp, gt, d, P)
+    xp, wp, lp = to_device(poly[:, :, None], w, lam, _s(S), torch.float64)
+    zp, _ = whs.whs_solve(xp, wp, lp, d, P, staged=_st(S))
+    _, glp, _ = whs.whs_backward(wp, lp, zp, gt, d, P, staged=_st(S))
     glp = from_device_rows(glp, P)
     gl = from_device_rows(gl, P)
     assert np.abs(glp).max() <= 1e-8 * np.abs(gl).max()

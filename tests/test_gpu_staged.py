@@ -1,0 +1,65 @@
+"""Series-contiguous calls (interleave 1) given the workspace of
+whs_interleave_workspace_bytes run the interleaved kernels on copies.  Their
+results must be bit-identical to the same call on interleaved tensors (the same
+kernels on the same values), which the oracle parity of the interleaved path
+then covers: every order, several bands (beyond the partition kernel's one),
+both weight kinds, both storage types, the adjoint, a series count that is not
+a multiple of 64, and the uneven-date calls, which take the contiguous layout
+only this way."""
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2604_00048_amd import synth, whs
+from tests._cases import from_device_rows, from_device_series, random_case, to_device
+
+pytestmark = pytest.mark.gpu
+DT = {"f64": torch.float64, "f32": torch.float32}
+CASES = [  # P, T, d, C, per_diff
+    (70, 300, 1, 1, True), (65, 500, 2, 3, False), (33, 350, 3, 1, True), (64, 260, 4, 2, True),
+    (130, 3288, 2, 1, True), (5, 40, 2, 10, False),
+]
+
+
+def both_layouts(x, w, lam, dtype):
+    return to_device(x, w, lam, 64, dtype), to_device(x, w, lam, 1, dtype)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("P,T,d,C,per_diff", CASES)
+def test_contiguous_calls_match_interleaved_bit_for_bit(P, T, d, C, per_diff, dt):
+    dtype = DT[dt]
+    x, w, lam = random_case(P, T, d, C=C, per_diff=per_diff, seed=P + T + d + C, dtype=dtype)
+    (x64, w64, l64), (x1, w1, l1) = both_layouts(x, w, lam, dtype)
+    z64, i64 = whs.whs_solve(x64, w64, l64, d, P)
+    z1, i1 = whs.whs_solve(x1, w1, l1, d, P)
+    g = torch.tensor(np.random.default_rng(P * 3 + C).normal(size=x.shape), dtype=dtype)
+    gx64, gl64, _ = whs.whs_backward(w64, l64, z64, synth.pack_series(g, 64).cuda(), d, P)
+    gx1, gl1, _ = whs.whs_backward(w1, l1, z1, synth.pack_series(g, 1).cuda(), d, P)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(i1.cpu().numpy(), i64.cpu().numpy())
+    np.testing.assert_array_equal(from_device_series(z1, P), from_device_series(z64, P))
+    np.testing.assert_array_equal(from_device_series(gx1, P), from_device_series(gx64, P))
+    np.testing.assert_array_equal(from_device_rows(gl1, P), from_device_rows(gl64, P))
+
+
+@pytest.mark.parametrize("d,C", [(1, 1), (2, 4), (3, 1)])
+def test_uneven_dates_contiguous_match_interleaved(d, C):
+    P, T, dtype = 77, 300, torch.float32
+    x, w, lam = random_case(P, T, d, C=C, per_diff=True, seed=31 * d + C, dtype=dtype)
+    times = 3.0 + np.cumsum(np.random.default_rng(d).integers(1, 4, size=T)).astype(np.float64)
+    coef = whs.whs_diff_coef(torch.tensor(times, device="cuda"), d)
+    (x64, w64, l64), (x1, w1, l1) = both_layouts(x, w, lam, dtype)
+    z64, _ = whs.whs_solve(x64, w64, l64, d, P, coef=coef)
+    z1, _ = whs.whs_solve(x1, w1, l1, d, P, coef=coef)
+    g = torch.tensor(np.random.default_rng(5).normal(size=x.shape), dtype=dtype)
+    gx64, gl64, _ = whs.whs_backward(w64, l64, z64, synth.pack_series(g, 64).cuda(), d, P, coef=coef)
+    gx1, gl1, _ = whs.whs_backward(w1, l1, z1, synth.pack_series(g, 1).cuda(), d, P, coef=coef)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(from_device_series(z1, P), from_device_series(z64, P))
+    np.testing.assert_array_equal(from_device_series(gx1, P), from_device_series(gx64, P))
+    np.testing.assert_array_equal(from_device_rows(gl1, P), from_device_rows(gl64, P))
+    # without the larger workspace the uneven-date calls refuse the contiguous layout
+    with pytest.raises(RuntimeError):
+        whs.whs_solve(x1, w1, l1, d, P, coef=coef, staged=False)
