@@ -11,7 +11,7 @@ import torch
 
 from oracle import whs_ref as R
 from paper_2604_00048_amd import synth, whs
-from tests._cases import assert_solution, from_device_rows, from_device_series, random_case, to_device
+from tests._cases import adjoint_spread, assert_solution, from_device_rows, from_device_series, random_case, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -126,7 +126,8 @@ def test_factor_is_the_cholesky_band(d, per_diff):
     a, b = from_device_series(z1, P), from_device_series(z2, P)
     assert (R.rel_err(a, b) < 1e-11).all()
     # and the adjoint with the exported factor matches the fused adjoint
-    g = torch.randn_like(xt)
+    g = torch.randn(xt.shape, generator=torch.Generator(device="cuda").manual_seed(11), device="cuda",
+                    dtype=xt.dtype)
     gx1, gl1, _ = whs.whs_backward(wt, lt, z1, g, d, P)
     gx2, gl2, _ = whs.whs_backward(wt, lt, z1, g, d, P, factor=F)
     torch.cuda.synchronize()
@@ -179,12 +180,16 @@ def test_autograd_function_matches_oracle():
     xt.requires_grad_(True)
     lt.requires_grad_(True)
     z = whs.smooth(xt, lt, wt, d, P)
-    g = torch.randn_like(z)
+    g = torch.randn(z.shape, generator=torch.Generator(device="cuda").manual_seed(21), device="cuda",
+                    dtype=z.dtype)
     (z * g).sum().backward()
     gn = from_device_series(g, P)
-    gx_ref, gl_ref, _ = R.vjp(x, w, lam, d, gn)
-    # norm-wise per series: single entries of -(D u)(D z) cancel to ~1e-12 of the series scale
+    gx_ref, gl_ref, _ = R.vjp(x, w, lam, d, gn, z=from_device_series(z.detach(), P))
+    # norm-wise per series against the oracle's adjoint at the kernel's z, within
+    # max(1e-9, 10 x the spread between the oracle's and LAPACK's solve of Omega u = g)
+    # (grad_lambda 10x: single entries of -(D u)(D z) cancel)
+    tol = np.maximum(1e-9, 10 * adjoint_spread(gn, w, lam, d))
     gx = from_device_series(xt.grad, P)
     gl = from_device_rows(lt.grad, P)
-    assert (np.abs(gx - gx_ref).max(axis=(1, 2)) / np.abs(gx_ref).max(axis=(1, 2))).max() < 1e-9
-    assert (np.abs(gl - gl_ref).max(axis=1) / np.abs(gl_ref).max(axis=1)).max() < 1e-9
+    assert (np.abs(gx - gx_ref).max(axis=(1, 2)) / np.abs(gx_ref).max(axis=(1, 2)) <= tol).all()
+    assert (np.abs(gl - gl_ref).max(axis=1) / np.abs(gl_ref).max(axis=1) <= 10 * tol).all()
