@@ -316,12 +316,22 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ in, 
   if (g == 0) pw[NOUT * NN + m] = bsum;
 }
 
-__global__ void k_wgrad_reduce(const float* __restrict__ part, int nparts, int len, float* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= len) return;
+// out[i] = sum_w part[w][i]: 64 outputs per workgroup, 16 lanes per output each
+// summing every 16th partial, then the 16 sums added in a fixed order
+__global__ __launch_bounds__(1024) void k_wgrad_reduce(const float* __restrict__ part, int nparts, int len,
+                                                       float* __restrict__ out) {
+  __shared__ float red[16][64];
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63), sl = threadIdx.x >> 6;
   float s = 0.f;
-  for (int w = 0; w < nparts; ++w) s += part[(int64_t)w * len + i];
-  out[i] = s;
+  if (col < len)
+    for (int w = sl; w < nparts; w += 16) s += part[(int64_t)w * len + col];
+  red[sl][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (sl == 0 && col < len) {
+    float t = 0.f;
+    for (int k = 0; k < 16; ++k) t += red[k][threadIdx.x];
+    out[col] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -529,7 +539,7 @@ int whs_net_conv_wgrad(const uint16_t* in, int cin, const uint16_t* gy, int cout
   else if (cin == 64 && cout == 16) hipLaunchKernelGGL((k_wgrad<64, 16>), dim3(parts), block, 0, s, in, gy, ws, P, T);
   else return -2;
   const int len = cout * KT * cin + cout;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(len, 256)), dim3(256), 0, s, ws, parts, len, grad);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(len, 64)), dim3(1024), 0, s, ws, parts, len, grad);
   return st(hipGetLastError());
 }
 
