@@ -37,7 +37,9 @@ def test_contiguous_calls_match_interleaved_bit_for_bit(P, T, d, C, per_diff, dt
     g = torch.tensor(np.random.default_rng(P * 3 + C).normal(size=x.shape), dtype=dtype)
     gx64, gl64, _ = whs.whs_backward(w64, l64, z64, synth.pack_series(g, 64).cuda(), d, P)
     gx1, gl1, _ = whs.whs_backward(w1, l1, z1, synth.pack_series(g, 1).cuda(), d, P)
+    _, gl1n, _ = whs.whs_backward(w1, l1, z1, synth.pack_series(g, 1).cuda(), d, P, need_x=False)
     torch.cuda.synchronize()
+    np.testing.assert_array_equal(from_device_rows(gl1n, P), from_device_rows(gl64, P))   # grad_x not requested
     np.testing.assert_array_equal(i1.cpu().numpy(), i64.cpu().numpy())
     np.testing.assert_array_equal(from_device_series(z1, P), from_device_series(z64, P))
     np.testing.assert_array_equal(from_device_series(gx1, P), from_device_series(gx64, P))
