@@ -32,7 +32,8 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __builtin_bit_cast(fl
 // ---------------------------------------------------------------------------
 // Convolution as implicit GEMM: out[t][n] = sum_{tap,c} Wt[n][tap][c] in[t+tap-4][c]
 // MODE 0: + bias, ReLU, bfloat16 out (P,T,NOUT)
-// MODE 1: + bias, FP32 out of channel 0 only (P,T)            (last layer)
+// MODE 1: + bias, FP32 out of channel 0 only (P,T)            (last layer; the
+//         launcher runs k_conv_last instead, which computes only that channel)
 // MODE 2: no bias, out *= (mask > 0), bfloat16 out (P,T,NOUT) (input gradient)
 // A tile is 64 time rows of one series; wave w computes output channels
 // 16w..16w+15 for all 64 rows (4 accumulator tiles).  Each workgroup loads
@@ -178,6 +179,59 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
     }
   }
   }  // tiles
+}
+
+// ---------------------------------------------------------------------------
+// Last layer, one real output channel: h[t] = bias + sum_{tap,c} W[tap][c]
+// in[t+tap-4][c] (64 input channels), FP32 out (P, T).  Vector arithmetic: a
+// 64-row tile's input window sits in LDS, four lanes share an output row (16
+// channels each, all nine taps) and add their sums with two lane swaps; the
+// weights of channel 0 are read from LDS as wave-wide broadcasts.  Channels
+// 1..15 of the padded weights are not read.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_conv_last(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wt,
+                                                   const float* __restrict__ bias, float* __restrict__ out, int T,
+                                                   int ntiles, int64_t total) {
+  constexpr int CIN = 64;
+  constexpr int ROWS = TM + 2 * HALO;
+  constexpr int RS = CIN + 8;  // LDS row stride in bf16 (16-byte pad)
+  __shared__ __attribute__((aligned(16))) uint16_t win[ROWS * RS];
+  __shared__ __attribute__((aligned(16))) uint16_t wl[KT * CIN];
+  for (int i = threadIdx.x; i < KT * CIN; i += blockDim.x) wl[i] = wt[i];  // output channel 0: (9, 64)
+  const float bv = bias ? bias[0] : 0.f;
+  const int r = threadIdx.x >> 2, q = threadIdx.x & 3;  // output row of the tile, channel quarter
+  for (int64_t tix = blockIdx.x; tix < total; tix += gridDim.x) {
+    const int64_t p = tix / ntiles;
+    const int t0 = (int)(tix - p * ntiles) * TM;
+    const uint16_t* inp = in + p * (int64_t)T * CIN;
+    __syncthreads();  // the weights are staged; the previous window is no longer read
+    for (int i = threadIdx.x; i < ROWS * (CIN / 8); i += blockDim.x) {
+      const int rr = i / (CIN / 8), c8 = i % (CIN / 8);
+      const int t = t0 - HALO + rr;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (t >= 0 && t < T) v = *reinterpret_cast<const u32x4*>(inp + (int64_t)t * CIN + 8 * c8);
+      *reinterpret_cast<u32x4*>(win + rr * RS + 8 * c8) = v;
+    }
+    __syncthreads();
+    float acc = 0.f;
+#pragma unroll
+    for (int tap = 0; tap < KT; ++tap) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const u32x4 a = *reinterpret_cast<const u32x4*>(win + (r + tap) * RS + 16 * q + 8 * h);
+        const u32x4 b = *reinterpret_cast<const u32x4*>(wl + tap * CIN + 16 * q + 8 * h);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          acc += bf2f((uint16_t)(a[k] & 0xffffu)) * bf2f((uint16_t)(b[k] & 0xffffu));
+          acc += bf2f((uint16_t)(a[k] >> 16)) * bf2f((uint16_t)(b[k] >> 16));
+        }
+      }
+    }
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    const int t = t0 + r;
+    if (q == 0 && t < T) out[p * (int64_t)T + t] = acc + bv;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -514,7 +568,10 @@ int whs_net_conv_fwd(const uint16_t* in, int cin, const uint16_t* w, const float
   hipLaunchKernelGGL((k_conv<CI, CO, MO>), grid, block, 0, s, in, w, bias, mask, out, T, ntiles, total)
   if (cin == 8 && cout == 64 && mode == 0) WHS_CONV(8, 64, 0);
   else if (cin == 64 && cout == 64 && mode == 0) WHS_CONV(64, 64, 0);
-  else if (cin == 64 && cout == 16 && mode == 1) WHS_CONV(64, 16, 1);
+  else if (cin == 64 && cout == 16 && mode == 1) {
+    // one real output channel: the vector kernel, 256 lanes per workgroup
+    hipLaunchKernelGGL(k_conv_last, grid, dim3(256), 0, s, in, w, bias, static_cast<float*>(out), T, ntiles, total);
+  }
   else if (cin == 64 && cout == 64 && mode == 2) WHS_CONV(64, 64, 2);
   else if (cin == 16 && cout == 64 && mode == 2) WHS_CONV(16, 64, 2);
   else return -2;
