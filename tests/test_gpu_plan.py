@@ -67,7 +67,8 @@ def test_graph_replay_matches_eager(f32_case):
     for k in range(3):
         z = torch.full_like(x, float("nan"))
         plan.graph_launch(w, lam, x, z)
-        junk = torch.randn(1 << 20, device="cuda").sum()  # unrelated eager work between replays
+        # unrelated eager work between replays
+        junk = torch.randn(1 << 20, device="cuda", generator=torch.Generator(device="cuda").manual_seed(k)).sum()
         torch.cuda.synchronize()
         for desc in descs:
             assert torch.equal(synth.unpack_group(z, desc), synth.unpack_group(z0, desc)), k
