@@ -1,0 +1,45 @@
+"""The measurement script's contract, checked without a GPU: one GPU only (a
+larger --gpus exits with a message and status 2), the algorithmic bytes behind
+``roofline.achieved`` (every API tensor once per pass at its storage type), and
+the traffic figures keyed to the sources of the kernels they were measured on."""
+
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_algorithmic_bytes_per_series():
+    # headline: T = 3288, d = 2, one band, FP32, one weight per difference row
+    fwd, bwd = bench.alg_bytes(3288, 2, 1, 4, True)
+    assert fwd == 4 * 3288 + 3288 + 4 * 3286 + 4 * 3288 == 42736
+    assert bwd == 3 * 4 * 3288 + 3288 + 2 * 4 * 3286 == 69032          # g, z, grad_x; w; lambda, grad_lambda
+    # scalar weight: one value per series in and out
+    fwd, bwd = bench.alg_bytes(365, 2, 10, 8, False)
+    assert fwd == 2 * 8 * 365 * 10 + 365 + 8
+    assert bwd == 3 * 8 * 365 * 10 + 365 + 2 * 8
+
+
+def test_traffic_is_keyed_to_the_kernel_sources():
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    h = bench.kernel_source_hash()
+    assert len(h) == 16
+    for key, v in rec.items():
+        assert v["bytes_per_launch"] > 0 and v["read_bytes"] + v["write_bytes"] == v["bytes_per_launch"]
+    # a figure is reported only while it describes the current sources
+    for kernel in ("whs_solve", "whs_backward"):
+        t = bench.measured_traffic(kernel, "heteroscedastic P=65536 T=3288 d=2 C=1")
+        stored = rec[f"{kernel}|heteroscedastic P=65536 T=3288 d=2 C=1"]
+        assert (t is not None) == (stored["source_hash"] == h)
