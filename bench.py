@@ -144,27 +144,42 @@ def bench_multiband(args):
     info = torch.empty(P, dtype=torch.int32, device=dev)
     desc = whs.make_desc(P, T, d, C, S, whs.WHS_F64 if dtype == torch.float64 else whs.WHS_F32, whs.WHS_LAMBDA_SCALAR)
     ws = torch.empty(whs.workspace_bytes(desc), dtype=torch.uint8, device=dev)
-    for _ in range(args.warmup):
+    if args.fwd_bwd:
+        # the adjoint too, against a seeded upstream gradient: g, grad_x, grad_lambda
+        g = torch.randn(pk.x.shape, generator=torch.Generator(device=dev).manual_seed(7), device=dev, dtype=dtype)
+        gx = torch.empty_like(pk.x)
+        gl = torch.empty(P, dtype=dtype, device=dev)
+
+    def step():
         whs.whs_solve(pk.x, pk.w, pk.lam, d, P, z=z, info=info, workspace=ws)
+        if args.fwd_bwd:
+            whs.whs_backward(pk.w, pk.lam, z, g, d, P, grad_x=gx, grad_lambda=gl, info=info, workspace=ws)
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
     e0, e1 = _events(2)
     e0.record()
     for _ in range(args.steps):
-        whs.whs_solve(pk.x, pk.w, pk.lam, d, P, z=z, info=info, workspace=ws)
+        step()
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     esz = 8 if dtype == torch.float64 else 4
-    fb, _ = alg_bytes(T, d, C, esz, False)
+    fb, bb = alg_bytes(T, d, C, esz, False)
+    if args.fwd_bwd:
+        fb += bb
     gbs = fb * P / (ms * 1e-3) / 1e9
     return {
-        "metric": "series/sec (T=3288,d=2,C=10 forward)", "value": P / (ms * 1e-3), "unit": "series/s",
+        "metric": f"series/sec (T=3288,d=2,C=10 {'fwd+bwd' if args.fwd_bwd else 'forward'})", "value": P / (ms * 1e-3),
+        "unit": "series/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"homoscedastic smoother forward: P={P}, T={T}, d=2, C=10 bands sharing one factor, "
+        "config": {"workload": f"homoscedastic smoother {'fwd+bwd' if args.fwd_bwd else 'forward'}: P={P}, T={T}, "
+                               f"d=2, C=10 bands sharing one factor, "
                                f"scalar lambda, {args.dtype.upper()} storage / FP64 arithmetic",
                    "P": P, "T": T, "d": d, "C": C, "storage": args.dtype},
-        "roofline": {"bound": "hbm", "kernel": "whs_solve", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "roofline": {"bound": "hbm", "kernel": "whs_solve + whs_backward" if args.fwd_bwd else "whs_solve",
+                     "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": gbs / PEAK_HBM_GBS, "traffic": None, "alg_bytes_per_series": fb, "ms_per_launch": ms},
         "failed_series": int((info != 0).sum().item()),
     }
@@ -277,6 +292,7 @@ def main():
     ap.add_argument("--T", type=int, default=3288)
     ap.add_argument("--d", type=int, default=2, help="difference order of the heteroscedastic workload")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--fwd-bwd", action="store_true", help="multiband workload: time the adjoint with the solve")
     ap.add_argument("--interleave", type=int, default=64)
     ap.add_argument("--in-place", action="store_true",
                     help="interleave 1: read the contiguous layout in place instead of through interleaved copies")

@@ -427,9 +427,19 @@ constexpr int tile_depth() {
   return 12;
 }
 
+// The fast solve of 2 or 3 bands in FP32 storage (order <= 2, even times) has
+// room for 16 steps: two bands with either weight kind, three with one weight
+// per series.  Never shallower than tile_depth, which sizes the checkpoints.
+template <int D, int C, bool TAB, int ES, bool BWD, bool PERDIFF>
+constexpr int fast_tile_depth() {
+  if (!TAB && !BWD && ES == 4 && D <= 2 && (C == 2 || (C == 3 && !PERDIFF))) return 16;
+  return tile_depth<D, C, TAB, ES>();
+}
+
 template <int D, int C, typename TS, Src SRC, Mode MODE, bool PERDIFF, bool TAB = false>
 hipError_t launch_fast(const LaunchDesc& L, int c0, int write_info, hipStream_t stream) {
-  constexpr int B = tile_depth<D, C, TAB, (int)sizeof(TS)>();
+  constexpr int B = fast_tile_depth<D, C, TAB, (int)sizeof(TS), MODE == Mode::Backward, PERDIFF>();
+  static_assert(B >= tile_depth<D, C, TAB, (int)sizeof(TS)>(), "checkpoints are sized for tile_depth");
   FastArgs f;
   f.P = L.P;
   f.T = L.T;
@@ -499,14 +509,16 @@ size_t ck_bytes_for(int64_t nb, int S, int T) {
 // kernel compiles without register spills: 5 bands for the solve of order
 // d <= 2, 3 bands otherwise (fast path: interleave a multiple of 64, weights
 // and mask given); the generic path (any interleave, or a given factor) uses
-// 2 and 1.
+// 2 and 1.  The FP32 solve with one weight per series (narrow) stops at 3
+// bands instead: its 16-step tiles move fewer checkpoint bytes per day than
+// the 8-step tiles of 5 bands.
 inline bool fast_path(const LaunchDesc& L) { return !L.fac && L.S % 64 == 0 && L.P < ((int64_t)1 << 31); }
 
-inline int max_group(int D, bool bwd) { return (!bwd && D <= 2) ? 5 : 3; }
+inline int max_group(int D, bool bwd, bool narrow) { return (!bwd && D <= 2) ? (narrow ? 3 : 5) : 3; }
 
-inline int next_group(int remaining, bool fast, int D, bool bwd) {
+inline int next_group(int remaining, bool fast, int D, bool bwd, bool narrow = false) {
   if (fast) {
-    const int g = max_group(D, bwd);
+    const int g = max_group(D, bwd, narrow);
     return remaining < g ? remaining : g;
   }
   return remaining >= 2 ? 2 : 1;
@@ -537,7 +549,7 @@ hipError_t run_groups(const LaunchDesc& L, hipStream_t stream) {
   constexpr bool kBwd = MODE == Mode::Backward;
   int c0 = 0;
   while (c0 < L.C) {
-    const int g = next_group(L.C - c0, fast, D, kBwd);
+    const int g = next_group(L.C - c0, fast, D, kBwd, sizeof(TS) == 4 && !PERDIFF);
     const int wi = c0 == 0;  // the first group writes info; later groups add to grad_lambda
     hipError_t e;
     if constexpr (SRC == Src::Fused) {

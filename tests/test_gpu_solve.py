@@ -47,12 +47,15 @@ CASES = [
     (130, 77, 2, 1, 32, True),
     (70, 53, 3, 1, 64, False),
     (64, 45, 4, 1, 64, True),
-    (65, 200, 2, 3, 64, False),    # RHS groups 2 + 1
-    (40, 120, 2, 10, 64, True),    # one group of 10
-    (33, 60, 3, 13, 16, True),     # groups 10 + 2 + 1
+    (65, 200, 2, 3, 64, False),    # one 3-band group (16-step tiles in FP32)
+    (40, 120, 2, 10, 64, True),    # solve groups 5 + 5, adjoint 3 + 3 + 3 + 1
+    (33, 60, 3, 13, 16, True),     # generic groups of 2 and 1
     (5, 3, 2, 1, 64, True),        # T = d + 1
     (9, 7, 1, 2, 4, False),        # one partial tile
     (3, 16, 2, 1, 1, True),        # S = 1, exactly one tile
+    (70, 150, 1, 3, 64, False),    # order 1, one 3-band group, ragged last tile
+    (66, 90, 2, 2, 64, True),      # a 2-band group with a weight per difference row
+    (64, 37, 1, 5, 64, False),     # solve groups 3 + 2 in FP32, 5 in FP64
 ]
 
 
