@@ -4,8 +4,9 @@ The workloads are generated exactly as bench.py generates them; the kernels
 run on the whole batch, and sampled series (spread over the batch, the last
 one included) are checked one by one against the oracle.  FP32 storage:
 per-series error <= 1e-4 and componentwise backward error <= 1e-6 for z,
-1e-4 relative for the adjoint (grad_lambda 1e-3) against the oracle's adjoint
-at the kernel's stored z.  Plus the finite-difference check of grad_lambda on
+1e-4 relative for the adjoint (grad_lambda 1e-3; for one weight per series,
+1e-4 of the summed magnitudes of its terms) against the oracle's adjoint at the
+kernel's stored z.  Plus the finite-difference check of grad_lambda on
 16 pixels of the headline batch (FP64 storage, central differences)."""
 
 import numpy as np
@@ -95,12 +96,18 @@ def test_headline_grad_lambda_by_finite_differences_on_16_pixels():
     assert (np.abs(fd - an) <= 1e-5 * scale + 1e-4 * np.abs(an)).all(), np.abs(fd - an) / scale
 
 
-def test_ten_band_forward_sampled():
+def test_ten_band_fwd_bwd_sampled():
+    # the ten-band workload as bench.py --workload multiband --fwd-bwd runs it: one
+    # workspace, the upstream gradient from the same seeded generator
     P, T, d, C = 262144, 3288, 2, 10
     pk = synth.generate_packed("multiband", P, S=64, dtype=torch.float32, device=DEV, chunk=8192, T=T, C=C)
-    z, info = whs.whs_solve(pk.x, pk.w, pk.lam, d, P)
+    g = torch.randn(pk.x.shape, generator=torch.Generator(device=DEV).manual_seed(7), device=DEV, dtype=torch.float32)
+    desc = whs.make_desc(P, T, d, C, 64, whs.WHS_F32, whs.WHS_LAMBDA_SCALAR)
+    ws = torch.empty(whs.workspace_bytes(desc), dtype=torch.uint8, device=DEV)
+    z, info = whs.whs_solve(pk.x, pk.w, pk.lam, d, P, workspace=ws)
+    gx, gl, info2 = whs.whs_backward(pk.w, pk.lam, z, g, d, P, workspace=ws)
     torch.cuda.synchronize()
-    assert int((info != 0).sum()) == 0
+    assert int((info != 0).sum()) == 0 and int((info2 != 0).sum()) == 0
     idx = sample(P, 12)
     x = series(pk.x, idx)
     w = rows(pk.w, idx)
@@ -110,7 +117,17 @@ def test_ten_band_forward_sampled():
     assert (iref == 0).all()
     assert R.rel_err(zs, zref).max() <= 1e-4
     assert R.backward_error(x, w, lam, d, zs).max() <= 1e-6
-    del pk, z
+    gs = series(g, idx)
+    gx_ref, gl_ref, _ = R.vjp(x, w, lam, d, gs, z=zs)
+    egx = np.abs(series(gx, idx) - gx_ref).max(axis=(1, 2)) / np.abs(gx_ref).max(axis=(1, 2))
+    assert egx.max() <= 1e-4, egx.max()
+    # one weight per series: grad_lambda sums 10 x 3286 signed terms (D u)(D z), so
+    # its error is measured against the sum of their magnitudes
+    u, _ = R.solve_band_rhs(gs, w, lam, d)
+    terms = (np.abs(R.apply_D(u, d)) * np.abs(R.apply_D(zs, d))).sum(axis=(1, 2))
+    egl = np.abs(gl[idx].double().cpu().numpy() - gl_ref) / terms
+    assert egl.max() <= 1e-4, egl.max()
+    del pk, z, g, gx, ws
 
 
 def test_uneven_batch_plan_sampled():
