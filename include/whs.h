@@ -182,8 +182,10 @@ int whs_gcv(const whs_desc* desc, const uint8_t* w, const void* x, const double*
  * path, no factor argument) with Omega = W + D^T Lambda D built from coef.
  * They require interleave a multiple of 64, or interleave 1 with a workspace
  * of at least whs_interleave_workspace_bytes(desc) (WHS_ERR_UNSUPPORTED
- * otherwise), and use the whs_workspace_bytes(desc) workspace.  Return codes,
- * info, aliasing and NaN conventions are those of whs_solve / whs_backward.
+ * otherwise), and use the whs_workspace_bytes(desc) workspace.  An empty
+ * batch (n_series 0) in either layout returns WHS_OK and touches nothing.
+ * Return codes, info, aliasing and NaN conventions are those of whs_solve /
+ * whs_backward.
  */
 int whs_diff_coef(const double* times, int32_t T, int32_t d, double* coef, void* stream);
 int whs_solve_coef(const whs_desc* desc, const double* coef, const uint8_t* w, const void* lambda,

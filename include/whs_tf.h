@@ -25,6 +25,10 @@
  * -2 = unsupported shape or mode, -3 = HIP launch error, -4 = workspace too
  * small.  Reductions over tokens write per-workgroup partial sums to the
  * workspace and add them in a fixed order (results are deterministic).
+ * Per-token calls accept an empty input (P or M = 0: 0, nothing launched);
+ * the four reductions (whs_tf_ln_bwd, whs_tf_wgrad, whs_tf_head_bwd,
+ * whs_tf_embed_bwd) need at least one token and return -1 otherwise, since
+ * they would leave their parameter gradients unwritten.
  */
 #ifndef WHS_TF_H
 #define WHS_TF_H

@@ -252,9 +252,9 @@ int whs_solve_coef(const whs_desc* desc, const double* coef, const uint8_t* w, c
                    void* z, int32_t* info, void* workspace, size_t workspace_bytes, void* stream) {
   int st = check_desc(desc);
   if (st != WHS_OK) return st;
+  if (desc->n_series == 0) return desc->interleave % 64 == 0 || desc->interleave == 1 ? WHS_OK : WHS_ERR_UNSUPPORTED;
   const bool stg = use_staged(desc, nullptr, workspace_bytes);
   if (!stg && (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31))) return WHS_ERR_UNSUPPORTED;
-  if (desc->n_series == 0) return WHS_OK;
   if (!coef || !w || !lambda || !x || !z) return WHS_ERR_ARG;
   const size_t e = elem(desc);
   if (!aligned(coef, 8) || !aligned(x, e) || !aligned(z, e) || !aligned(lambda, e) || !aligned(info, 4))
@@ -277,9 +277,9 @@ int whs_backward_coef(const whs_desc* desc, const double* coef, const uint8_t* w
                       size_t workspace_bytes, void* stream) {
   int st = check_desc(desc);
   if (st != WHS_OK) return st;
+  if (desc->n_series == 0) return desc->interleave % 64 == 0 || desc->interleave == 1 ? WHS_OK : WHS_ERR_UNSUPPORTED;
   const bool stg = use_staged(desc, nullptr, workspace_bytes);
   if (!stg && (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31))) return WHS_ERR_UNSUPPORTED;
-  if (desc->n_series == 0) return WHS_OK;
   if (!coef || !w || !lambda || !z || !g) return WHS_ERR_ARG;
   const size_t e = elem(desc);
   if (!aligned(coef, 8) || !aligned(z, e) || !aligned(g, e) || !aligned(grad_x, e) || !aligned(grad_lambda, e) ||

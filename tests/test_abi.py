@@ -97,6 +97,19 @@ def test_empty_batch_is_a_noop():
     L = whs.lib()
     assert L.whs_backward(ctypes.byref(desc), None, None, None, None, None, None, None, None, None, 0, None) == 0
     assert L.whs_factor(ctypes.byref(desc), None, None, None, None, None) == 0
+    # every entry point, both layouts it accepts: no pointer is read and no launch made
+    for S in (64, 1):
+        e = whs.make_desc(0, 50, 2, 1, S, 0, 0)
+        assert L.whs_solve_coef(ctypes.byref(e), None, None, None, None, None, None, None, 0, None) == 0
+        assert L.whs_backward_coef(ctypes.byref(e), None, None, None, None, None, None, None, None, None, 0,
+                                   None) == 0
+        assert L.whs_interleave_workspace_bytes(ctypes.byref(e)) == 0
+    assert L.whs_solve_coef(ctypes.byref(whs.make_desc(0, 50, 2, 1, 32, 0, 0)), None, None, None, None, None,
+                            None, None, 0, None) == -2                                  # layout still checked
+    assert L.whs_gcv(ctypes.byref(desc), None, None, None, 21, None, None, None, None, 0, None) == 0
+    assert L.whs_variance(ctypes.byref(desc), None, None, None, None, None, 0, None) == 0
+    assert L.whs_gcv_workspace_bytes(ctypes.byref(desc)) == 0
+    assert L.whs_variance_workspace_bytes(ctypes.byref(desc)) == 0
 
 
 def test_workspace_and_factor_sizes():
@@ -255,3 +268,14 @@ def test_transformer_entry_points_validate_arguments():
     assert L.whs_tf_head_bwd(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 4, 9, 64, 2, -6.0, 10.0, FAKE, FAKE, FAKE, 0, 4,
                              None) == -4
     assert L.whs_tf_cast(FAKE, 0, 64, FAKE, None, None) == -1
+    # empty inputs: per-token calls return 0 without launching, reductions refuse
+    assert L.whs_tf_embed(FAKE, FAKE, 0, 9, 4, 64, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == 0
+    assert L.whs_tf_ln_fwd(FAKE, 0, FAKE, FAKE, FAKE, FAKE, None) == 0
+    assert L.whs_tf_attn_fwd(FAKE, 0, 9, FAKE, FAKE, None) == 0
+    assert L.whs_tf_head_fwd(FAKE, 0, 9, FAKE, 64, 2, -6.0, 10.0, FAKE, FAKE, FAKE, FAKE, None) == 0
+    big = 1 << 30
+    assert L.whs_tf_ln_bwd(FAKE, FAKE, FAKE, FAKE, FAKE, 0, FAKE, FAKE, FAKE, big, 4, None) == -1
+    assert L.whs_tf_wgrad(FAKE, 0, 192, FAKE, 64, 0, FAKE, FAKE, big, 5, None) == -1
+    assert L.whs_tf_embed_bwd(FAKE, FAKE, 0, 5, FAKE, FAKE, big, 4, None) == -1
+    assert L.whs_tf_head_bwd(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 0, 9, 64, 2, -6.0, 10.0, FAKE, FAKE, FAKE, big, 4,
+                             None) == -1
