@@ -189,7 +189,15 @@ def attention_term_scales(q, k, v, lse, go, o):
 
 @pytest.mark.parametrize("T", [1, 37, 128, 129, 300, 643])
 def test_attention_forward_backward(T):
-    P = 2
+    check_attention(2, T)
+
+
+def test_attention_longest_sequence():
+    # the largest T the attention calls accept: 32 staged key chunks, 32 query blocks
+    check_attention(1, 4096)
+
+
+def check_attention(P, T):
     qkv, (q, k, v) = attn_inputs(P, T)
     o = torch.empty((P * T, E), dtype=torch.int16, device=dev)
     lse = torch.empty((P, X.H, T), dtype=torch.float32, device=dev)
