@@ -158,6 +158,29 @@ def test_failures_and_ignored_unobserved_values():
     assert (R.rel_err(z[4:], zref[4:]) < 1e-10).all()
 
 
+@pytest.mark.parametrize("S", [64, 1])
+def test_long_series(S):
+    # 200,000 steps: 8,334 tiles of checkpoints per series, one full block of 64
+    # series and a ragged one; the contiguous layout goes through the interleaved copies
+    P, T, d = 65, 200_000, 2
+    x, w, lam = random_case(P, T, d, per_diff=True, seed=200 + S, dtype=torch.float32)
+    xt, wt, lt = to_device(x, w, lam, S, torch.float32)
+    z, info = whs.whs_solve(xt, wt, lt, d, P)
+    g = torch.tensor(np.random.default_rng(S).normal(size=x.shape), dtype=torch.float32)
+    gx, gl, info2 = whs.whs_backward(wt, lt, z, synth.pack_series(g, S).cuda(), d, P)
+    torch.cuda.synchronize()
+    zc = from_device_series(z, P)
+    zref, iref = R.solve_band(x, w, lam, d)
+    np.testing.assert_array_equal(info.cpu().numpy(), iref)
+    np.testing.assert_array_equal(info2.cpu().numpy(), iref)
+    assert_solution(zc, zref, x, w, lam, d, False)
+    gx_ref, gl_ref, _ = R.vjp(x, w, lam, d, g.double().numpy(), z=zc)
+    ex = np.abs(from_device_series(gx, P) - gx_ref).max(axis=(1, 2)) / np.abs(gx_ref).max(axis=(1, 2))
+    el = np.abs(from_device_rows(gl, P) - gl_ref).max(1) / np.abs(gl_ref).max(1)
+    assert ex.max() <= 1e-4, ex.max()
+    assert el.max() <= 1e-3, el.max()
+
+
 def test_empty_batch_and_determinism_and_in_place():
     P, T, d, S = 200, 150, 2, 64
     x, w, lam = random_case(P, T, d, per_diff=True, seed=9)
