@@ -43,19 +43,23 @@ size_t checkpoint_bytes(int64_t P, int S, int T, int D, int C) {
       rem -= g;
     }
   }
-  // the uneven-time grouping (fast path only)
-  for (int rem = C; rem > 0;) {
-    const int g = next_group_tab(rem);
-    size_t b = 0;
-    switch (D) {
-      case 1: b = ck_bytes_tab_d<1>(nb, S, T, g); break;
-      case 2: b = ck_bytes_tab_d<2>(nb, S, T, g); break;
-      case 3: b = ck_bytes_tab_d<3>(nb, S, T, g); break;
-      case 4: b = ck_bytes_tab_d<4>(nb, S, T, g); break;
-      default: return 0;
+  // the uneven-time groupings (fast path only): the solve's, and the adjoint's
+  // for either storage type and weight kind
+  for (int variant = 0; variant < 5; ++variant) {
+    const bool bwd = variant > 0, f64 = variant > 2, perdiff = variant % 2 == 1;
+    for (int rem = C; rem > 0;) {
+      const int g = next_group_tab(rem, bwd, D, f64, perdiff);
+      size_t b = 0;
+      switch (D) {
+        case 1: b = ck_bytes_tab_d<1>(nb, S, T, g); break;
+        case 2: b = ck_bytes_tab_d<2>(nb, S, T, g); break;
+        case 3: b = ck_bytes_tab_d<3>(nb, S, T, g); break;
+        case 4: b = ck_bytes_tab_d<4>(nb, S, T, g); break;
+        default: return 0;
+      }
+      if (b > mx) mx = b;
+      rem -= g;
     }
-    if (b > mx) mx = b;
-    rem -= g;
   }
   return mx;
 }

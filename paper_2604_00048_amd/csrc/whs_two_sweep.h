@@ -535,12 +535,29 @@ inline size_t ck_bytes_d(int64_t nb, int S, int T, int g) {
   }
 }
 
-// band groups of the uneven-time kernels
-inline int next_group_tab(int remaining) { return remaining >= 4 ? 4 : 1; }
+// Band groups of the uneven-time kernels: the solve takes 4 and 1.  The
+// adjoint takes the widest group whose kernel compiles without register
+// spills: 4 bands only for FP32 storage with a weight per difference row at
+// order <= 2, else 2 bands (orders 1 and 2; order 3 except FP64 with one weight
+// per series; order 4 with a weight per difference row), else 1.
+inline int tab_max_group(bool bwd, int D, bool f64, bool perdiff) {
+  if (!bwd) return 4;
+  if (D <= 2 && !f64 && perdiff) return 4;
+  if (D <= 2 || (D == 3 && !(f64 && !perdiff)) || (D == 4 && perdiff)) return 2;
+  return 1;
+}
+
+inline int next_group_tab(int remaining, bool bwd = false, int D = 1, bool f64 = false, bool perdiff = true) {
+  const int g = tab_max_group(bwd, D, f64, perdiff);
+  if (remaining >= g) return g;
+  return remaining >= 2 && g >= 2 && bwd ? 2 : 1;
+}
 
 template <int D>
 inline size_t ck_bytes_tab_d(int64_t nb, int S, int T, int g) {
-  return g == 4 ? ck_bytes_for<D, 4, true>(nb, S, T) : ck_bytes_for<D, 1, true>(nb, S, T);
+  if (g == 4) return ck_bytes_for<D, 4, true>(nb, S, T);
+  if (g == 2) return ck_bytes_for<D, 2, true>(nb, S, T);
+  return ck_bytes_for<D, 1, true>(nb, S, T);
 }
 
 template <int D, typename TS, Src SRC, Mode MODE, bool PERDIFF>
@@ -582,15 +599,23 @@ hipError_t run_groups(const LaunchDesc& L, hipStream_t stream) {
 }
 
 // Uneven sample times (a coefficient table for D): fast path only, built for
-// 4 and 1 bands per launch.
+// 4 and 1 bands per launch, and 2 for the adjoint.
 template <int D, typename TS, Mode MODE, bool PERDIFF>
 hipError_t run_groups_tab(const LaunchDesc& L, hipStream_t stream) {
+  constexpr bool kBwd = MODE == Mode::Backward;
   int c0 = 0;
   while (c0 < L.C) {
-    const int g = next_group_tab(L.C - c0);
+    const int g = next_group_tab(L.C - c0, kBwd, D, sizeof(TS) == 8, PERDIFF);
     const int wi = c0 == 0;
-    const hipError_t e = g == 4 ? launch_fast<D, 4, TS, Src::Fused, MODE, PERDIFF, true>(L, c0, wi, stream)
-                                : launch_fast<D, 1, TS, Src::Fused, MODE, PERDIFF, true>(L, c0, wi, stream);
+    hipError_t e;
+    if (g == 4) {
+      e = launch_fast<D, 4, TS, Src::Fused, MODE, PERDIFF, true>(L, c0, wi, stream);
+    } else if (g == 2) {
+      if constexpr (kBwd) e = launch_fast<D, 2, TS, Src::Fused, MODE, PERDIFF, true>(L, c0, wi, stream);
+      else e = hipErrorInvalidValue;  // never chosen for the solve
+    } else {
+      e = launch_fast<D, 1, TS, Src::Fused, MODE, PERDIFF, true>(L, c0, wi, stream);
+    }
     if (e != hipSuccess) return e;
     c0 += g;
   }

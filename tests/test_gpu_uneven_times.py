@@ -46,8 +46,12 @@ CASES = [  # P, T, d, C, per_diff
     (64, 75, 1, 1, False),
     (70, 101, 3, 1, True),
     (65, 90, 4, 1, True),
-    (64, 60, 2, 5, False),            # a group of 4 bands plus one
+    (64, 60, 2, 5, False),            # solve groups 4 + 1, adjoint 2 + 2 + 1
     (100, 33, 2, 1, False),
+    (66, 80, 2, 4, True),             # adjoint: one group of 4 in FP32, 2 + 2 in FP64
+    (64, 70, 3, 3, False),            # adjoint 2 + 1 in FP32, 1 + 1 + 1 in FP64
+    (65, 90, 4, 2, True),             # adjoint: one group of 2
+    (70, 66, 1, 3, False),            # adjoint 2 + 1
 ]
 
 
