@@ -421,7 +421,7 @@ __global__ __launch_bounds__(256) void k_two_sweep(Args a) {
 template <int D, int C, bool TAB = false, int ES = 4>
 constexpr int tile_depth() {
   if (C != 1) return 8;
-  if (TAB) return D <= 2 ? 16 : 12;
+  if (TAB) return D == 1 ? 16 : D == 4 ? 8 : 12;  // as deep as the adjoint with a weight per difference row
   if (D <= 2) return ES == 4 ? 24 : 16;
   if (D == 3) return ES == 4 ? 16 : 12;
   return 12;
@@ -429,10 +429,13 @@ constexpr int tile_depth() {
 
 // The fast solve of 2 or 3 bands in FP32 storage (order <= 2, even times) has
 // room for 16 steps: two bands with either weight kind, three with one weight
-// per series.  Never shallower than tile_depth, which sizes the checkpoints.
+// per series.  With uneven times, one band takes 16 steps (order <= 2) or 12
+// except in the adjoint with a weight per difference row.  Never shallower
+// than tile_depth, which sizes the checkpoints.
 template <int D, int C, bool TAB, int ES, bool BWD, bool PERDIFF>
 constexpr int fast_tile_depth() {
   if (!TAB && !BWD && ES == 4 && D <= 2 && (C == 2 || (C == 3 && !PERDIFF))) return 16;
+  if (TAB && C == 1 && !(BWD && PERDIFF)) return D <= 2 ? 16 : 12;
   return tile_depth<D, C, TAB, ES>();
 }
 
