@@ -114,9 +114,10 @@ def test_empty_batch_is_a_noop():
 
 def test_workspace_and_factor_sizes():
     # order 2, one band: 2 + 1 + 2 = 5 doubles per tile per series; the largest
-    # user is the uneven-time kernel with tiles of 16 steps
+    # user is the uneven-time adjoint with a weight per difference row, whose
+    # tiles are 12 steps
     desc = whs.make_desc(100, 365, 2, 1, 64, 0, 1)
-    tiles = (365 + 15) // 16
+    tiles = (365 + 11) // 12
     assert whs.workspace_bytes(desc) == 2 * tiles * 5 * 64 * 8
     assert whs.lib().whs_factor_bytes(ctypes.byref(desc)) == 128 * 3 * 365 * 8
 
