@@ -69,7 +69,10 @@ typedef struct {
   int32_t T;           /* series length, T > d                                    */
   int32_t d;           /* difference order = sub-diagonals of Omega, 1..4         */
   int32_t n_rhs;       /* C >= 1 bands sharing one factor                         */
-  int32_t interleave;  /* S >= 1 (64 = one wavefront per block)                   */
+  int32_t interleave;  /* S >= 1 (64 = one wavefront per block); for S a multiple */
+                       /* of 64 every per-block array (T*S*C values, T*S flags,   */
+                       /* each kernel's checkpoints of one block) must stay under */
+                       /* 2^31 bytes, else WHS_ERR_UNSUPPORTED (use S = 64)       */
   int32_t dtype;       /* whs_dtype: storage type of x, z, g, lambda and grads    */
   int32_t lambda_kind; /* whs_lambda_kind                                         */
 } whs_desc;

@@ -305,6 +305,40 @@ def cholesky_band(AB: np.ndarray, w: np.ndarray | None = None):
     return Lb, info
 
 
+def cholesky_band_inplace(AB: np.ndarray):
+    """Cholesky factor in lower band storage by Alg. 1's update order (Sec. III-A).
+
+    A second, independently organised factorisation next to ``cholesky_band``:
+    Alg. 1 works in place on the band array and is right-looking.  For each
+    column ``t``: the pivot ``omega = AB[0, t]`` becomes ``sqrt(omega)``, the
+    column's sub-diagonal entries ``v = AB[1:, t]`` are divided by
+    ``sqrt(omega)``, and every later column ``t+1+u`` that ``v`` reaches
+    (``u < d`` and ``t+1+u < T``) loses the outer-product term: its band
+    entries ``AB[i, t+1+u] = Omega[t+1+u+i, t+1+u]`` for ``i = 0..d-1-u``
+    decrease by ``v[u+i] v[u] / omega`` (``v`` is the column before scaling).
+    ``AB[p, i, t]`` is ``Omega[t+i, t]`` with a zero tail (Fig. 2).  Returns
+    ``(Lb, info)`` like ``cholesky_band``; the input is not modified.
+    """
+    A = np.array(AB, dtype=np.float64, copy=True)
+    P, dp1, T = A.shape
+    d = dp1 - 1
+    info = np.zeros(P, dtype=np.int64)
+    for t in range(T):
+        omega = A[:, 0, t].copy()
+        bad = (info == 0) & ~(np.isfinite(omega) & (omega > 0))
+        info[bad] = t + 1
+        omega = np.where(omega > 0, omega, np.nan)
+        v = A[:, 1:, t].copy()          # Omega[t+1.., t] after the earlier updates
+        root = np.sqrt(omega)
+        A[:, 0, t] = root
+        A[:, 1:, t] = v / root[:, None]
+        for u in range(min(d, T - t - 1)):
+            col = t + 1 + u
+            n = d - u                   # entries of column col still inside v's reach
+            A[:, :n, col] -= v[:, u:u + n] * (v[:, u] / omega)[:, None]
+    return A, info
+
+
 # ---------------------------------------------------------------------------
 # adjoint (eq. (4), eq. (5))
 # ---------------------------------------------------------------------------
@@ -514,10 +548,3 @@ def rel_err(z: np.ndarray, zref: np.ndarray) -> np.ndarray:
     num = np.abs(z3 - r3).max(axis=(1, 2))
     den = np.abs(r3).max(axis=(1, 2))
     return num / np.where(den > 0, den, 1.0)
-
-
-def heldout_mse_maxe(z: np.ndarray, x: np.ndarray, mask: np.ndarray):
-    """Reconstruction MSE and MaxE over the points in ``mask`` (Sec. IV-D)."""
-    m = np.asarray(mask) != 0
-    e = (np.asarray(z, dtype=np.float64) - np.asarray(x, dtype=np.float64))[m]
-    return float(np.mean(e ** 2)), float(np.max(np.abs(e)))

@@ -10,6 +10,26 @@ constexpr int kMaxD = 4;
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+size_t elem(const whs_desc* d) { return d->dtype == WHS_F64 ? 8 : 4; }
+
+// Interleaves that are a multiple of 64 run the kernels that address one block
+// of S series through 32-bit buffer ranges, with byte offset 2^31 marking the
+// padding lanes of a partial block: every per-block array (x, z, g, grad_x,
+// w, lambda, and each kernel's checkpoint area) must stay below 2^31 bytes.
+// Other interleaves use 64-bit addressing and have no such limit.
+bool block_ranges_fit(const whs_desc* d) {
+  if (d->interleave % 64 != 0) return true;
+  constexpr uint64_t kLim = (uint64_t)1 << 31;
+  const uint64_t rows = (uint64_t)d->T * (uint64_t)d->interleave;  // < 2^62
+  if (rows >= kLim) return false;                                  // w; also bounds the products below
+  if (rows * (uint64_t)d->n_rhs * elem(d) >= kLim) return false;   // x, z, g, grad_x (lambda is smaller)
+  const int64_t S = d->interleave;
+  if (whs::checkpoint_bytes(S, (int)S, d->T, d->d, d->n_rhs) >= kLim) return false;
+  if (whs::gcv_checkpoint_bytes(S, (int)S, d->T, d->d) >= kLim) return false;
+  if (whs::var_checkpoint_bytes(S, (int)S, d->T, d->d) >= kLim) return false;
+  return true;
+}
+
 int check_desc(const whs_desc* d) {
   if (!d) return WHS_ERR_ARG;
   if (d->n_series < 0 || d->T < 1 || d->d < 1 || d->n_rhs < 1 || d->interleave < 1) return WHS_ERR_ARG;
@@ -19,10 +39,9 @@ int check_desc(const whs_desc* d) {
   if (d->T <= d->d) return WHS_ERR_ARG;
   // grid of ceil(P/256) blocks must fit one launch dimension
   if (d->n_series > (int64_t)0x7fffffff * 256) return WHS_ERR_UNSUPPORTED;
+  if (!block_ranges_fit(d)) return WHS_ERR_UNSUPPORTED;
   return WHS_OK;
 }
-
-size_t elem(const whs_desc* d) { return d->dtype == WHS_F64 ? 8 : 4; }
 
 whs::LaunchDesc make_launch(const whs_desc* d) {
   whs::LaunchDesc L{};
@@ -145,7 +164,8 @@ const char* whs_status_str(int status) {
   switch (status) {
     case WHS_OK: return "ok";
     case WHS_ERR_ARG: return "invalid argument (descriptor, null or misaligned pointer)";
-    case WHS_ERR_UNSUPPORTED: return "unsupported configuration (order d > 4 or too many series)";
+    case WHS_ERR_UNSUPPORTED:
+      return "unsupported configuration (order d > 4, too many series, or a block of interleaved series of 2 GiB or more)";
     case WHS_ERR_HIP: return "HIP runtime or launch error";
     case WHS_ERR_WORKSPACE: return "workspace missing or smaller than whs_workspace_bytes()";
     default: return "unknown status";

@@ -286,6 +286,10 @@ int whs_plan_create(whs_plan** out, const whs_group* groups, int32_t n_groups, i
     if (G.n_series < 0 || G.T < 1 || G.d < 1 || G.T <= G.d) return WHS_ERR_ARG;
     if (G.d > 4) return WHS_ERR_UNSUPPORTED;
     if (G.x_off < 0 || G.w_off < 0 || G.lam_off < 0 || G.info_off < 0) return WHS_ERR_ARG;
+    // blocks of 64 series are addressed through 32-bit buffer ranges (x, z at
+    // 8 bytes per value, and the per-wavefront checkpoint slot at up to 14
+    // FP64 fields per 8-step tile): both stay below 2^31 bytes
+    if ((int64_t)G.T * 64 * 8 * 2 >= ((int64_t)1 << 31)) return WHS_ERR_UNSUPPORTED;
     gd.push_back(GroupDev{G.x_off, G.w_off, G.lam_off, G.info_off, G.n_series, G.T, G.d});
     const int64_t nb = (G.n_series + 63) / 64;
     if (nb > 0x7fffffff) return WHS_ERR_UNSUPPORTED;

@@ -80,6 +80,39 @@ def test_order_above_four_is_unsupported():
     assert _solve_raw(desc, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 30) == -2
 
 
+@pytest.mark.parametrize("P,T,d,C,S,dt", [
+    (262144, 3288, 2, 10, 262144, 0),    # the ten-band batch as one block: 34 GB of x per block
+    (262144, 3288, 2, 1, 262144, 0),     # one band: 3.4 GB of x, 2.9 GB of checkpoints per block
+    (1048576, 3288, 2, 1, 1048576, 0),
+    (640, 100000, 4, 5, 640, 1),         # long many-band series: x and checkpoints past 2 GiB per block
+])
+def test_blocks_past_32_bit_ranges_are_unsupported(P, T, d, C, S, dt):
+    # the fast kernels address one block through 32-bit buffer ranges, with byte
+    # offset 2^31 marking padding lanes: such descriptors are refused, never run
+    L = whs.lib()
+    desc = whs.make_desc(P, T, d, C, S, dt, 1)
+    assert whs.workspace_bytes(desc) == 0
+    assert _solve_raw(desc, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 40) == -2
+    assert L.whs_backward(ctypes.byref(desc), FAKE, FAKE, None, FAKE, FAKE, FAKE, FAKE, None, FAKE, 1 << 40,
+                          None) == -2
+    assert L.whs_solve_coef(ctypes.byref(desc), FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, 1 << 40, None) == -2
+    assert L.whs_variance(ctypes.byref(desc), FAKE, FAKE, FAKE, None, FAKE, 1 << 40, None) == -2
+    # the same batch in blocks of 64 series is accepted
+    ok = whs.make_desc(P, T, d, C, 64, dt, 1)
+    assert whs.workspace_bytes(ok) > 0
+
+
+def test_block_range_limit_edges():
+    # one block of S = 2^16 series at T = 8192 in FP32: x is exactly 2^31 bytes (refused);
+    # at T = 4000 every per-block array is below 2^31 bytes, checkpoints included (accepted)
+    assert whs.workspace_bytes(whs.make_desc(65536, 8192, 1, 1, 65536, 0, 0)) == 0
+    assert whs.workspace_bytes(whs.make_desc(65536, 4000, 1, 1, 65536, 0, 0)) > 0
+    # plan groups: 64-series blocks of very long series are refused as well
+    h = ctypes.c_void_p()
+    g = (whs.WhsGroup * 1)(whs.WhsGroup(64, 1 << 21, 2, 0, 0, 0, 0))
+    assert whs.lib().whs_plan_create(ctypes.byref(h), g, 1, 1, 0, 0, 64) == -2
+
+
 def test_null_and_misaligned_pointers():
     desc = whs.make_desc(10, 50, 2, 1, 64, 0, 0)
     assert _solve_raw(desc, None, FAKE, FAKE, FAKE, FAKE, 1 << 30) == -1

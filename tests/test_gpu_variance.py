@@ -1,9 +1,7 @@
 """GPU parity of whs_variance (diagonal of Omega^{-1}, the posterior variance)
 against the oracle's selected inverse.  FP64 storage: per-series max-norm
-relative error <= max(1e-9, 2 eps kappa_2(Omega)), the first-order bound on the
-inverse of a matrix factored with a backward error of a few eps (two correct
-FP64 computations already differ by more than 1e-9 on ill-conditioned series:
-the oracle and a dense LU inverse differ by up to eps kappa / 6 here).  FP32
+relative error <= max(1e-9, 10x the distance between the oracle and the
+diagonal of LAPACK's banded inverse), the same spread rule as the solve.  FP32
 storage: 1e-5 (both sides see the same FP32-rounded weights; the kernel's
 arithmetic is FP64, only the stored result is rounded)."""
 
@@ -13,12 +11,9 @@ import torch
 
 from oracle import whs_ref as R
 from paper_2604_00048_amd import synth, whs
-from tests._cases import random_case, to_device
+from tests._cases import inverse_diag_spread, random_case, spread_bar, to_device
 
 pytestmark = pytest.mark.gpu
-
-
-EPS = np.finfo(np.float64).eps
 
 
 def _assert_close(var, ref, w, lam, d, f64):
@@ -28,8 +23,9 @@ def _assert_close(var, ref, w, lam, d, f64):
         return
     bad = rel > 1e-9
     if bad.any():
-        kappa = np.linalg.cond(R.omega_dense(w[bad], np.asarray(lam)[bad], d))
-        assert (rel[bad] <= 2 * EPS * kappa).all(), (rel[bad].max(), (2 * EPS * kappa).min())
+        spread = inverse_diag_spread(w[bad], np.asarray(lam)[bad], d, ref[bad])
+        fail, allow = spread_bar(rel[bad], spread, 1e-9)
+        assert fail.size == 0, ("err", rel[bad][fail], "allowed", allow[fail], "spread", spread[fail])
 
 
 def _run(w, lam, d, P, dt):
@@ -43,8 +39,7 @@ def _run(w, lam, d, P, dt):
 @pytest.mark.parametrize("per_diff", [True, False])
 @pytest.mark.parametrize("P,T,d", [(130, 200, 2), (64, 37, 1), (70, 101, 3), (65, 90, 4), (1, 17, 2)])
 def test_variance_parity(P, T, d, per_diff, dt):
-    _, w, lam = random_case(P, T, d, per_diff=per_diff, seed=3 * P + T + d, p_obs=0.25, dtype=dt,
-                            lam_hi=3.0 if d >= 3 else 4.0)
+    _, w, lam = random_case(P, T, d, per_diff=per_diff, seed=3 * P + T + d, p_obs=0.25, dtype=dt)
     var, info = _run(w, lam, d, P, dt)
     ref, rinfo = R.posterior_variance(w, lam, d)
     np.testing.assert_array_equal(info, rinfo)
@@ -57,7 +52,8 @@ def test_variance_failures_and_heavy_smoothing():
     _, w, lam = random_case(P, T, d, per_diff=True, seed=11)
     w[5] = 0
     w[5, 40] = 1                 # one observation: singular, info = T
-    lam[9, 30] = -1e6            # a large negative weight: Omega is indefinite, a pivot fails
+    lam[9, 30] = -1e6            # a large negative weight: Omega is indefinite by a wide margin, so the
+                                 # first failing pivot is not a rounding decision
     lam[12, :] = 1e8             # heavy smoothing: variance of the straight-line fit
     var, info = _run(w, lam, d, P, torch.float64)
     ref, rinfo = R.posterior_variance(w, lam, d)

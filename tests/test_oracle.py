@@ -273,6 +273,39 @@ def test_P9_cholesky_band_is_numpy_cholesky(d):
     np.testing.assert_allclose(Lb[:, 0], np.sqrt(Dp), rtol=1e-9)
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_P9_alg1_update_order_is_numpy_cholesky(d):
+    # the right-looking in-place factorisation (Alg. 1's order) against LAPACK's
+    # dense Cholesky and against the left-looking column definition
+    T = 23
+    _, w, lam = _rand_case(3, T, d, per_diff=True, seed=90 + d)
+    AB = R.omega_band(w, lam, d)
+    AB0 = AB.copy()
+    Lb, info = R.cholesky_band_inplace(AB)
+    assert (info == 0).all()
+    np.testing.assert_array_equal(AB, AB0)  # the caller's array is untouched
+    dense = R.omega_dense(w, lam, d)
+    for p in range(3):
+        Lc = np.linalg.cholesky(dense[p])
+        for i in range(d + 1):
+            ref = np.concatenate([np.diagonal(Lc, -i), np.zeros(i)])
+            # two FP64 factorisations of a matrix with condition up to ~1e9 (d = 4)
+            np.testing.assert_allclose(Lb[p, i], ref, rtol=0, atol=1e-10 * np.abs(Lc).max())
+    Lb2, _ = R.cholesky_band(AB)
+    np.testing.assert_allclose(Lb, Lb2, rtol=0, atol=1e-10 * np.abs(Lb2).max())
+
+
+def test_P9_alg1_update_order_hand_example_and_failure():
+    # T = 3, d = 1, Omega = [[4, 2, 0], [2, 5, 3], [0, 3, 10]]: L = [[2], [1, 2], [0, 1.5, sqrt(7.75)]]
+    AB = np.array([[[4.0, 5.0, 10.0], [2.0, 3.0, 0.0]]])
+    Lb, info = R.cholesky_band_inplace(AB)
+    assert info[0] == 0
+    np.testing.assert_allclose(Lb[0], [[2.0, 2.0, np.sqrt(7.75)], [1.0, 1.5, 0.0]], rtol=1e-15)
+    # a zero second pivot: Omega = [[1, 1], [1, 1]]
+    _, info = R.cholesky_band_inplace(np.array([[[1.0, 1.0], [1.0, 0.0]]]))
+    assert info[0] == 2
+
+
 def test_P10_backward_error_small():
     for d in (1, 2, 3):
         x, w, lam = _rand_case(8, 300, d, p_obs=0.1, per_diff=True, seed=70 + d)
@@ -462,6 +495,45 @@ def test_P12_effective_dimension_limits(d):
     wf = np.ones((1, T), dtype=np.uint8)
     _, ed1, _ = R.gcv_scores(x[:1], wf, np.array([1e-9]), d)
     np.testing.assert_allclose(ed1[0, 0], T, rtol=1e-6)
+
+
+@pytest.mark.parametrize("lam", [0.3, 7.0, 2e3])
+def test_P12_gcv_score_first_order_full_mask_closed_form(lam):
+    # d = 1, w = 1: Omega = I + lam D^T D is diagonalised by the orthonormal DCT-II
+    # with eigenvalues 1 + 4 lam sin^2(pi k / 2T).  So ED = sum_k 1/(1 + mu_k),
+    # RSS = sum_k (mu_k / (1 + mu_k))^2 X_k^2 with X the DCT of x, and
+    # GCV = T RSS / (T - ED)^2 (m = T observed points).
+    T = 48
+    x = np.random.default_rng(17).normal(size=(3, T)) + np.linspace(0, 2, T)
+    w = np.ones((3, T), dtype=np.uint8)
+    k = np.arange(T)
+    mu = 4.0 * lam * np.sin(np.pi * k / (2 * T)) ** 2
+    X = scipy.fft.dct(x, type=2, norm="ortho", axis=1)
+    ed = (1.0 / (1.0 + mu)).sum()
+    rss = ((mu / (1.0 + mu)) ** 2 * X ** 2).sum(axis=1)
+    scores, eds, rsss = R.gcv_scores(x, w, np.array([lam]), 1)
+    np.testing.assert_allclose(eds[:, 0], ed, rtol=1e-12)
+    np.testing.assert_allclose(rsss[:, 0], rss, rtol=1e-10)
+    np.testing.assert_allclose(scores[:, 0], T * rss / (T - ed) ** 2, rtol=1e-10)
+
+
+def test_P12_gcv_argmin_matches_closed_form_scan():
+    # the same closed form over the whole grid picks the same weight
+    T = 64
+    r = np.random.default_rng(23)
+    x = np.sin(np.arange(T) / 6.0)[None, :] + 0.3 * r.normal(size=(4, T))
+    w = np.ones((4, T), dtype=np.uint8)
+    grid = R.gcv_grid()
+    k = np.arange(T)
+    X = scipy.fft.dct(x, type=2, norm="ortho", axis=1)
+    ref = np.zeros((4, grid.size))
+    for gi, lam in enumerate(grid):
+        mu = 4.0 * lam * np.sin(np.pi * k / (2 * T)) ** 2
+        ed = (1.0 / (1.0 + mu)).sum()
+        ref[:, gi] = T * ((mu / (1.0 + mu)) ** 2 * X ** 2).sum(axis=1) / (T - ed) ** 2
+    lam_best, idx, scores = R.gcv_select(x, w, grid, 1)
+    np.testing.assert_allclose(scores, ref, rtol=1e-9)
+    np.testing.assert_array_equal(idx, np.argmin(ref, axis=1))
 
 
 def test_gcv_grid_and_tie_rule():
