@@ -47,64 +47,61 @@ def from_device_rows(lt, P):
     return synth.unpack_rows(lt.cpu(), P).double().numpy()
 
 
-def lapack_spread(x, w, lam, d, zref, coef=None):
-    """Norm-wise distance between the oracle and LAPACK's banded solver per series
-    (how far two correct FP64 solvers already differ on this input)."""
-    import scipy.linalg
-    AB = R.omega_band(w, lam, d, coef)
-    out = np.zeros(x.shape[0])
-    for p in range(x.shape[0]):
-        ref = scipy.linalg.solveh_banded(AB[p], np.where(w[p][:, None] != 0, x[p], 0.0), lower=True)
-        out[p] = np.abs(ref - zref[p]).max() / max(np.abs(ref).max(), 1e-300)
-    return out
+# Backward error assumed for an FP64 result that is not output in full (the
+# adjoint's u = Omega^{-1} g is seen only through W u and (D u)(D z); the
+# variance is a diagonal of Omega^{-1}): 1e-15, about five times what banded
+# LDL^T reaches on these systems (the oracle's own solutions sit near 2e-16).
+BETA_UNSEEN = 1e-15
 
 
-def adjoint_spread(g, w, lam, d, coef=None):
-    """Norm-wise distance per series between the oracle's u = Omega^{-1} g and
-    LAPACK's banded solve of the same system."""
-    import scipy.linalg
+def solve_bar(z, zref, x, w, lam, d, floor=1e-10, coef=None):
+    """The FP64 parity bar of a solve, per series.  A series passes if its
+    norm-wise error against the oracle is <= ``floor``; otherwise its error
+    against the solution refined in extended precision must stay within twice
+    what its own componentwise backward error allows (the exact Oettli-Prager
+    bound ``beta |Omega^{-1}| (|Omega||z| + |Wx|)``): forward errors of any
+    backward-stable FP64 solver grow with the conditioning of Omega, and two
+    such solvers can share most of theirs, so neither 1e-10 nor their distance
+    bounds a third.  Returns (failing rows, error, allowed)."""
+    err = R.rel_err(z, zref)
+    bad = np.nonzero(err > floor)[0]
+    if bad.size == 0:
+        return bad, err[bad], np.full(0, floor)
+    b = np.where(np.asarray(w)[bad][:, :, None] != 0, np.asarray(x)[bad].reshape(bad.size, w.shape[1], -1), 0.0)
+    lb = np.asarray(lam)[bad]
+    zt = R.solve_band_refined(b, w[bad], lb, d, coef).astype(np.float64)
+    et = R.rel_err(z[bad], zt)
+    allow = np.maximum(floor, 2 * R.solution_error_bound(b, w[bad], lb, d, z[bad], coef))
+    fail = et > allow
+    return bad[fail], et[fail], allow[fail]
+
+
+def adjoint_tol(g, w, lam, d, floor=1e-9, coef=None):
+    """Per-series FP64 bar for the adjoint against the oracle's: ``floor``, or
+    twice the Oettli-Prager bound of ``u = Omega^{-1} g`` for a backward error of
+    ``BETA_UNSEEN`` on each of the two sides, whichever is larger."""
     g3 = g if g.ndim == 3 else g[:, :, None]
     u, _ = R.solve_band_rhs(g3, w, lam, d, coef)
-    AB = R.omega_band(w, lam, d, coef)
-    out = np.zeros(g3.shape[0])
-    for p in range(g3.shape[0]):
-        ref = scipy.linalg.solveh_banded(AB[p], g3[p], lower=True)
-        out[p] = np.abs(ref - u[p]).max() / max(np.abs(ref).max(), 1e-300)
-    return out
+    return np.maximum(floor, 2 * R.solution_error_bound(g3, w, lam, d, u, coef, beta=2 * BETA_UNSEEN))
 
 
-def inverse_diag_spread(w, lam, d, ref, coef=None):
-    """Norm-wise distance per series between the oracle's diag(Omega^{-1}) and the
-    diagonal of LAPACK's banded solve against the identity."""
-    import scipy.linalg
-    AB = R.omega_band(w, lam, d, coef)
-    out = np.zeros(w.shape[0])
-    for p in range(w.shape[0]):
-        inv = scipy.linalg.solveh_banded(AB[p], np.eye(w.shape[1]), lower=True)
-        dg = np.diagonal(inv)
-        out[p] = np.abs(dg - ref[p]).max() / max(np.abs(dg).max(), 1e-300)
-    return out
-
-
-def spread_bar(err, spread, floor):
-    """The FP64 parity bar: per series, err <= max(floor, 10 x the distance between
-    two correct FP64 solvers on the same input).  Returns the failing rows."""
-    allow = np.maximum(floor, 10 * spread)
-    return np.nonzero(err > allow)[0], allow
+def inverse_diag_tol(w, lam, d, floor=1e-9, coef=None):
+    """Per-series FP64 bar for diag(Omega^{-1}) against the oracle's: ``floor``,
+    or twice the first-order error bound of the diagonal under a componentwise
+    perturbation of ``BETA_UNSEEN`` on each side, whichever is larger."""
+    return np.maximum(floor, 2 * R.inverse_diag_error_bound(w, lam, d, 2 * BETA_UNSEEN, coef))
 
 
 def assert_solution(z, zref, x, w, lam, d, f64: bool, info=None, coef=None):
-    """FP64: per-series error <= max(1e-10, 10 x LAPACK spread); FP32 storage:
-    <= 1e-4.  Always: componentwise backward error <= 1e-13 (FP64) / 1e-6 (FP32),
-    which does not depend on the conditioning."""
+    """FP64: ``solve_bar`` (1e-10, or the bound the result's own backward error
+    gives on ill-conditioned series); FP32 storage: <= 1e-4.  Always:
+    componentwise backward error <= 1e-13 (FP64) / 1e-6 (FP32), which does not
+    depend on the conditioning."""
     ok = np.ones(z.shape[0], bool) if info is None else (info == 0)
     err = R.rel_err(z[ok], zref[ok])
     if f64:
-        bad = err > 1e-10
-        if bad.any():
-            spread = lapack_spread(x[ok][bad], w[ok][bad], np.asarray(lam)[ok][bad], d, zref[ok][bad], coef)
-            fail, allow = spread_bar(err[bad], spread, 1e-10)
-            assert fail.size == 0, ("err", err[bad][fail], "allowed", allow[fail], "spread", spread[fail])
+        fail, et, allow = solve_bar(z[ok], zref[ok], x[ok], w[ok], np.asarray(lam)[ok], d, 1e-10, coef)
+        assert fail.size == 0, ("rows", fail, "err", et, "allowed", allow)
         be = R.backward_error(x[ok], w[ok], np.asarray(lam)[ok], d, z[ok], coef)
         assert be.max() <= 1e-13, be.max()
     else:

@@ -1,7 +1,7 @@
 """GPU parity of whs_variance (diagonal of Omega^{-1}, the posterior variance)
 against the oracle's selected inverse.  FP64 storage: per-series max-norm
-relative error <= max(1e-9, 10x the distance between the oracle and the
-diagonal of LAPACK's banded inverse), the same spread rule as the solve.  FP32
+relative error <= max(1e-9, twice the first-order error of diag(Omega^{-1})
+under componentwise perturbations of Omega of 1e-15 on each side).  FP32
 storage: 1e-5 (both sides see the same FP32-rounded weights; the kernel's
 arithmetic is FP64, only the stored result is rounded)."""
 
@@ -11,7 +11,7 @@ import torch
 
 from oracle import whs_ref as R
 from paper_2604_00048_amd import synth, whs
-from tests._cases import inverse_diag_spread, random_case, spread_bar, to_device
+from tests._cases import inverse_diag_tol, random_case, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -21,11 +21,11 @@ def _assert_close(var, ref, w, lam, d, f64):
     if not f64:
         assert rel.max() < 1e-5, rel.max()
         return
-    bad = rel > 1e-9
-    if bad.any():
-        spread = inverse_diag_spread(w[bad], np.asarray(lam)[bad], d, ref[bad])
-        fail, allow = spread_bar(rel[bad], spread, 1e-9)
-        assert fail.size == 0, ("err", rel[bad][fail], "allowed", allow[fail], "spread", spread[fail])
+    bad = np.nonzero(rel > 1e-9)[0]
+    if bad.size:
+        allow = inverse_diag_tol(w[bad], np.asarray(lam)[bad], d)
+        fail = rel[bad] > allow
+        assert not fail.any(), ("rows", bad[fail], "err", rel[bad][fail], "allowed", allow[fail])
 
 
 def _run(w, lam, d, P, dt):

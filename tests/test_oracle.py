@@ -726,3 +726,90 @@ def test_P14_uneven_grad_lambda_by_finite_differences():
         lm[0, k] -= h
         fd = (np.sum(g * R.solve_band(x, w, lp, d, coef)[0]) - np.sum(g * R.solve_band(x, w, lm, d, coef)[0])) / (2 * h)
         assert abs(fd - gl[0, k]) <= 1e-5 * abs(fd) + 1e-6 * np.abs(gl).max(), (k, fd, gl[0, k])
+
+
+# --- accuracy metrics used by the FP64 parity bars ------------------------------
+
+
+def _ill_case(d):
+    """An ill-conditioned series with exactly representable inputs: a long gap,
+    large integer weights, dyadic values."""
+    T = 16
+    w = [1, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 0, 1, 1, 1]
+    lam = [Fraction(10 ** (3 + (k % 3))) for k in range(T - d)]
+    x = [Fraction((5 * t * t - 3 * t + 1) % 17, 8) for t in range(T)]
+    return T, w, lam, x
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_refined_solution_matches_exact_rational_solution(d):
+    T, w, lam, x = _ill_case(d)
+    ex = np.array([float(v) for v in _exact_solve(T, d, w, lam, x)])
+    wa = np.array([w], dtype=np.uint8)
+    la = np.array([[float(v) for v in lam]])
+    b = np.array([[float(v) if w[t] else 0.0 for t, v in enumerate(x)]])
+    plain, _ = R.solve_band(b, wa, la, d)
+    ref = R.solve_band_refined(b, wa, la, d).astype(np.float64)
+    e_plain = np.abs(plain[0] - ex).max() / np.abs(ex).max()
+    e_ref = np.abs(ref[0] - ex).max() / np.abs(ex).max()
+    kappa = np.linalg.cond(R.omega_dense(wa, la, d)[0])
+    assert e_plain > 1e-12  # the case is ill-conditioned enough to matter
+    # limiting accuracy of refinement with a 64-bit-significand residual
+    assert e_ref <= 4 * kappa * 2.0 ** -64 and e_ref <= e_plain / 100, (e_ref, e_plain, kappa)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_solution_error_bound_covers_the_true_error(d):
+    T, w, lam, x = _ill_case(d)
+    ex = np.array([float(v) for v in _exact_solve(T, d, w, lam, x)])
+    wa = np.array([w], dtype=np.uint8)
+    la = np.array([[float(v) for v in lam]])
+    b = np.array([[float(v) if w[t] else 0.0 for t, v in enumerate(x)]])
+    plain, _ = R.solve_band(b, wa, la, d)
+    rng = np.random.default_rng(d)
+    for z in (plain[0], plain[0] * (1 + 1e-9 * rng.standard_normal(T)), ex + 1e-6 * np.abs(ex).max() * np.eye(T)[5]):
+        err = np.abs(z - ex).max() / np.abs(z).max()
+        bound = R.solution_error_bound(b, wa, la, d, z[None])[0]
+        assert err <= bound * (1 + 1e-6), (err, bound)
+        assert bound <= 1e4 * max(err, 1e-16) * np.linalg.cond(R.omega_dense(wa, la, d)[0]), (err, bound)
+
+
+def test_solution_error_bound_with_a_given_backward_error_scales_linearly():
+    x, w, lam = _rand_case(3, 40, 2, per_diff=True, seed=4)
+    b = np.where(w != 0, x, 0.0)
+    z, _ = R.solve_band(b, w, lam, 2)
+    b1 = R.solution_error_bound(b, w, lam, 2, z, beta=1e-15)
+    b2 = R.solution_error_bound(b, w, lam, 2, z, beta=2e-15)
+    np.testing.assert_allclose(b2, 2 * b1, rtol=1e-12)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_refined_inverse_diagonal_matches_exact_rational_inverse(d):
+    T, w, lam, _ = _ill_case(d)
+    wa = np.array([w], dtype=np.uint8)
+    la = np.array([[float(v) for v in lam]])
+    # exact inverse by Gauss-Jordan on Fractions against the identity
+    c = [(-1) ** (d - j) * comb(d, j) for j in range(d + 1)]
+    A = [[Fraction(0)] * T for _ in range(T)]
+    for t in range(T):
+        A[t][t] += Fraction(w[t])
+    for k in range(T - d):
+        for a in range(d + 1):
+            for bb in range(d + 1):
+                A[k + a][k + bb] += lam[k] * c[a] * c[bb]
+    M = [row[:] + [Fraction(int(i == j)) for j in range(T)] for i, row in enumerate(A)]
+    for col in range(T):
+        piv = next(r for r in range(col, T) if M[r][col] != 0)
+        M[col], M[piv] = M[piv], M[col]
+        for r in range(T):
+            if r != col and M[r][col] != 0:
+                f = M[r][col] / M[col][col]
+                M[r] = [a - f * q for a, q in zip(M[r], M[col])]
+    ex = np.array([float(M[i][T + i] / M[i][i]) for i in range(T)])
+    ref = R.inverse_diag_refined(wa, la, d)[0]
+    kappa = np.linalg.cond(R.omega_dense(wa, la, d)[0])
+    assert np.abs(ref - ex).max() / np.abs(ex).max() <= 4 * kappa * 2.0 ** -64
+    var, _ = R.posterior_variance(wa, la, d)
+    err = np.abs(var[0] - ex).max() / np.abs(ex).max()
+    bound = R.inverse_diag_error_bound(wa, la, d, 1e-15)[0]
+    assert err <= bound, (err, bound)
