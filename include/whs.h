@@ -131,6 +131,24 @@ int whs_solve(const whs_desc* desc, const uint8_t* w, const void* lambda,
               void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * whs_solve_noalloc -- whs_solve on the fused path (factor NULL) for callers
+ * that cannot allocate device memory or size a workspace: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * inter-sweep checkpoints live in a library-owned device array of
+ * whs_solve_noalloc_max_bytes() (64 MiB) per GPU, held until the process
+ * ends; the call itself allocates nothing.  Inputs, outputs and info are the
+ * caller's, as in whs_solve.  Returns WHS_ERR_UNSUPPORTED when
+ * whs_workspace_bytes(desc) exceeds that size (e.g. about 11,000 series of
+ * T = 3288 at d = 2, one band, FP32), WHS_ERR_HIP if the array's address
+ * cannot be obtained.  Every call on one GPU shares that GPU's array: calls
+ * that overlap in time on one GPU (different streams, or threads) race and
+ * must be ordered by the caller.
+ */
+size_t whs_solve_noalloc_max_bytes(void);
+int whs_solve_noalloc(const whs_desc* desc, const uint8_t* w, const void* lambda, const void* x, void* z,
+                      int32_t* info, void* stream);
+
+/*
  * whs_backward -- adjoint of whs_solve against an upstream gradient g
  * (eq. (4), eq. (5)): with u = Omega^{-1} g (one more banded solve),
  *     grad_x      = W u                      (exactly 0 where w_t = 0)

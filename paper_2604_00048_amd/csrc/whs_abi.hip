@@ -1,6 +1,8 @@
 // C-ABI entry points of libwhs: argument validation and dispatch.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "whs.h"
 #include "whs_kernels.h"
 
@@ -156,6 +158,30 @@ hipError_t backward_staged(const whs_desc* d, const double* coef, const uint8_t*
   return err;
 }
 
+// Workspace of whs_solve_noalloc: a library-owned device array, one copy per
+// GPU, held until the process ends.  Host code never passes its name to a
+// kernel or a copy: the address of each device's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's copy of `scratch` (nullptr on failure).
+void* scratch_for_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -229,6 +255,22 @@ int whs_solve(const whs_desc* desc, const uint8_t* w, const void* lambda, const 
   L.info = info;
   L.ws = static_cast<double*>(workspace);
   return hip_status(whs::launch_solve(L, static_cast<hipStream_t>(stream)));
+}
+
+size_t whs_solve_noalloc_max_bytes(void) { return kNoallocScratchBytes; }
+
+int whs_solve_noalloc(const whs_desc* desc, const uint8_t* w, const void* lambda, const void* x, void* z,
+                      int32_t* info, void* stream) {
+  int st = check_desc(desc);
+  if (st != WHS_OK) return st;
+  if (desc->n_series == 0) return WHS_OK;
+  if (whs_workspace_bytes(desc) > kNoallocScratchBytes) return WHS_ERR_UNSUPPORTED;
+  if (!w || !lambda || !x || !z) return WHS_ERR_ARG;
+  void* ws = scratch_for_current_device();
+  if (!ws) return WHS_ERR_HIP;
+  // the scratch array is passed as an ordinary workspace: whs_solve picks the
+  // interleaved copies for interleave 1 when they fit, and allocates nothing
+  return whs_solve(desc, w, lambda, nullptr, x, z, info, ws, kNoallocScratchBytes, stream);
 }
 
 int whs_backward(const whs_desc* desc, const uint8_t* w, const void* lambda, const double* factor, const void* z,

@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libwhs.so")
 
 WHS_F32, WHS_F64 = 0, 1
 WHS_LAMBDA_SCALAR, WHS_LAMBDA_PER_DIFF = 0, 1
+WHS_OK, WHS_ERR_ARG, WHS_ERR_UNSUPPORTED, WHS_ERR_HIP, WHS_ERR_WORKSPACE = 0, -1, -2, -3, -4
 
 
 class WhsDesc(ctypes.Structure):
@@ -68,6 +69,8 @@ SIGNATURES = {
     "whs_factor": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP]),
     "whs_solve": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "whs_backward": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "whs_solve_noalloc_max_bytes": (_SZ, []),
+    "whs_solve_noalloc": (ctypes.c_int, [_DP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "whs_gcv_workspace_bytes": (_SZ, [_DP]),
     "whs_gcv": (ctypes.c_int, [_DP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "whs_diff_coef": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP]),
@@ -253,6 +256,27 @@ def whs_solve(x: torch.Tensor, w: torch.Tensor, lam: torch.Tensor | None, d: int
         return z, info
     _check(lib().whs_solve(ctypes.byref(desc), _ptr(w), _ptr(lam), _ptr(factor), _ptr(x), _ptr(z), _ptr(info),
                            _ptr(ws), ws.numel() * ws.element_size(), _stream(x.device)), "whs_solve")
+    return z, info
+
+
+def whs_solve_noalloc(x: torch.Tensor, w: torch.Tensor, lam: torch.Tensor, d: int, P: int | None = None,
+                      z: torch.Tensor | None = None, info: torch.Tensor | None = None):
+    """``whs_solve`` through the entry point that allocates nothing (its
+    checkpoints use the library's own device array).  Returns ``(z, info)``;
+    pass ``z`` and ``info`` to keep this call free of allocations too."""
+    _need_gpu(x, w, lam, z, info)
+    nb, T, C, S, P = _geometry(x, P)
+    if tuple(w.shape) != (nb, T, S) or w.dtype != torch.uint8:
+        raise ValueError(f"w must be uint8 of shape {(nb, T, S)}")
+    if lam.dtype != x.dtype:
+        raise TypeError("lambda must have the storage dtype of x")
+    desc = make_desc(P, T, d, C, S, _dtype_code(x), _lambda_kind(lam, P, nb, T, d, S))
+    if z is None:
+        z = torch.empty_like(x)
+    if info is None:
+        info = torch.empty(P, dtype=torch.int32, device=x.device)
+    _check(lib().whs_solve_noalloc(ctypes.byref(desc), _ptr(w), _ptr(lam), _ptr(x), _ptr(z), _ptr(info),
+                                   _stream(x.device)), "whs_solve_noalloc")
     return z, info
 
 

@@ -313,3 +313,18 @@ def test_transformer_entry_points_validate_arguments():
     assert L.whs_tf_embed_bwd(FAKE, FAKE, 0, 5, FAKE, FAKE, big, 4, None) == -1
     assert L.whs_tf_head_bwd(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 0, 9, 64, 2, -6.0, 10.0, FAKE, FAKE, FAKE, big, 4,
                              None) == -1
+
+
+def test_noalloc_entry_point_checks_sizes_before_touching_the_device():
+    L = whs.lib()
+    assert L.whs_solve_noalloc_max_bytes() == 64 << 20
+    big = whs.make_desc(65536, 3288, 2, 1, 64, whs.WHS_F32, whs.WHS_LAMBDA_PER_DIFF)
+    assert L.whs_workspace_bytes(ctypes.byref(big)) > L.whs_solve_noalloc_max_bytes()
+    assert L.whs_solve_noalloc(ctypes.byref(big), FAKE, FAKE, FAKE, FAKE, None, None) == whs.WHS_ERR_UNSUPPORTED
+    small = whs.make_desc(100, 365, 2, 1, 64, whs.WHS_F32, whs.WHS_LAMBDA_PER_DIFF)
+    assert L.whs_solve_noalloc(ctypes.byref(small), None, FAKE, FAKE, FAKE, None, None) == whs.WHS_ERR_ARG
+    assert L.whs_solve_noalloc(ctypes.byref(small), FAKE, FAKE, FAKE, None, None, None) == whs.WHS_ERR_ARG
+    empty = whs.make_desc(0, 365, 2, 1, 64, whs.WHS_F32, whs.WHS_LAMBDA_PER_DIFF)
+    assert L.whs_solve_noalloc(ctypes.byref(empty), None, None, None, None, None, None) == whs.WHS_OK
+    bad = whs.make_desc(100, 2, 2, 1, 64, whs.WHS_F32, whs.WHS_LAMBDA_PER_DIFF)  # T <= d
+    assert L.whs_solve_noalloc(ctypes.byref(bad), FAKE, FAKE, FAKE, FAKE, None, None) == whs.WHS_ERR_ARG
