@@ -66,6 +66,64 @@ def measured_traffic(kernel: str, workload: str):
     return e.get("bytes_per_launch")
 
 
+def _counter_rows(root: str):
+    """(kernel name, counter name, value) of every dispatch in rocprofv3's csv output under ``root``."""
+    import csv
+    import glob
+    out = []
+    for f in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                out.append((r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def _mean_counter(rows, name_part: str, counter: str):
+    vals = [v for k, c, v in rows if name_part in k and c == counter]
+    if not vals:
+        raise SystemExit(f"no {counter} samples for kernels matching {name_part!r}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def ingest_counters(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, P, T, d):
+    """HBM bytes per launch of the two headline kernels from FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch), each scaled by what the counter reads for a plain 256 MiB
+    device copy (``--calibrate-copy``)."""
+    copy_kib = (256 << 20) / 1024
+    cf, _ = _mean_counter(_counter_rows(cal_fetch_dir), "copy", "FETCH_SIZE")
+    cw, _ = _mean_counter(_counter_rows(cal_write_dir), "copy", "WRITE_SIZE")
+    fs, ws = copy_kib / cf, copy_kib / cw
+    fr, wr = _counter_rows(fetch_dir), _counter_rows(write_dir)
+    workload = f"heteroscedastic P={P} T={T} d={d} C=1"
+    fb, bb = alg_bytes(T, d, 1, 4, True)
+    rec = {}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            rec = json.load(f)
+    print(f"calibration: copy of 256 MiB reads FETCH_SIZE {cf:.0f} KiB, WRITE_SIZE {cw:.0f} KiB "
+          f"-> scales {fs:.3f} / {ws:.3f}")
+    print("| API call | kernel | dispatches | algorithmic GB | HBM read GB | HBM write GB | traffic / algorithmic |")
+    print("|---|---|---|---|---|---|---|")
+    for call, bwd, alg in (("whs_solve", "false", fb), ("whs_backward", "true", bb)):
+        part = f"k_fast<{d}, 1, "
+        names = sorted({k for k, c, v in fr if part in k and f"float, {bwd}, true, false>" in k})
+        if len(names) != 1:
+            raise SystemExit(f"expected one {call} kernel, found {names}")
+        kname = names[0]
+        f_kib, n = _mean_counter(fr, kname, "FETCH_SIZE")
+        w_kib, _ = _mean_counter(wr, kname, "WRITE_SIZE")
+        rd, wt = f_kib * 1024 * fs, w_kib * 1024 * ws
+        rec[f"{call}|{workload}"] = {"source_hash": kernel_source_hash(), "kernel": kname,
+                                     "bytes_per_launch": rd + wt, "read_bytes": rd, "write_bytes": wt,
+                                     "fetch_scale": fs, "write_scale": ws}
+        print(f"| {call} | `{kname}` | {n} | {alg * P / 1e9:.3f} | {rd / 1e9:.3f} | {wt / 1e9:.3f} | "
+              f"{(rd + wt) / (alg * P):.2f} |")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(f"wrote {path} (kernel source hash {kernel_source_hash()})")
+
+
 def _cpu_worker(args):
     import numpy as np
     from oracle import whs_ref as R
@@ -306,8 +364,16 @@ def main():
                     help="learned workloads: fresh series scored (262144, or 32768 for the transformer)")
     ap.add_argument("--acq", type=int, default=280, help="transformer workload: acquisitions per series")
     ap.add_argument("--bands", type=int, default=4, help="transformer workload: spectral bands")
+    ap.add_argument("--heldout-steps", type=int, default=150,
+                    help="default workload: training steps (4096 series each) of the learned form scored in 'heldout'")
+    ap.add_argument("--heldout-series", type=int, default=65536,
+                    help="default workload: fresh series on which the learned and GCV-plain forms are scored")
+    ap.add_argument("--no-heldout", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+                    help="read rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv output of the default workload and of "
+                         "--calibrate-copy, write profiles/traffic.json and print the per-kernel table")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 256 MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -316,6 +382,11 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (pixels shard across GPUs "
                                    "with no exchange, see the design notes)"}), flush=True)
         sys.exit(2)
+
+    if args.ingest_counters:
+        P = args.P or 65536
+        ingest_counters(*args.ingest_counters, P=P, T=args.T, d=args.d)
+        return
 
     if args.calibrate_copy:
         import torch
@@ -487,7 +558,28 @@ def bench_hetero(args):
             "value": rate_l, "unit": "series/s", "cores": used_l, "kind": "LAPACK dpbsv (scipy solveh_banded)",
             "sample": f"{nl} of the {P} series, forward + adjoint solve per series, {used_l} processes, {secs_l:.1f} s",
         }
+    if not args.no_heldout:
+        out["heldout"] = heldout_clause(dev, args.heldout_steps, args.heldout_series)
     return out
+
+
+def heldout_clause(dev, steps: int, n_series: int):
+    """The metric's third clause, outside the timed region: the learned form (per-day
+    weights from the convolution network) trained for a bounded number of steps
+    through the smoother, then scored with the GCV-plain form on the same held-out
+    points of fresh series, with each form's throughput (network + solve; GCV over
+    21 weights + solve)."""
+    import torch
+    from paper_2604_00048_amd import learned
+    t0 = time.perf_counter()
+    L = learned.train(dev, steps=steps, batch_size=4096, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    ev = learned.evaluate(L, dev, n_series=n_series, chunk=min(n_series, 65536))
+    ev.update({"train_steps": steps, "train_batch": 4096, "train_seconds": t_train,
+               "note": "RMSE in data units over 10 % of the observed points of every fresh series, hidden from "
+                       "both forms; series/s per form on chunks of up to 65,536 series"})
+    return ev
 
 
 if __name__ == "__main__":

@@ -22,26 +22,26 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)nbytes, kRsrcWord3);
 }
 
-template <typename TS>
-__device__ __forceinline__ TS bload(__amdgpu_buffer_rsrc_t r, uint32_t off);
-template <>
-__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+// Cache policy of a buffer access.  kStream marks data touched once more at
+// most, far in the future or never (the reverse sweep's inputs, results,
+// checkpoints): non-temporal, so it does not displace lines still to be reused.
+constexpr int kKeep = 0;
+constexpr int kStream = 2;  // NT bit of the gfx950 cache-policy operand
+
+template <typename TS, int POL = kKeep>
+__device__ __forceinline__ TS bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(TS) == 4)
+    return __builtin_bit_cast(TS, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, POL));
+  else
+    return __builtin_bit_cast(TS, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, POL));
 }
-template <>
-__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-template <typename TS>
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, TS v);
-template <>
-__device__ __forceinline__ void bstore<float>(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, off, 0, 0);
-}
-template <>
-__device__ __forceinline__ void bstore<double>(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) int, v), r, off,
-                                        0, 0);
+template <typename TS, int POL = kKeep>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, TS v) {
+  if constexpr (sizeof(TS) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, off, 0, POL);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) int, v), r, off, 0,
+                                          POL);
 }
 
 // positive normal or subnormal: the only acceptable pivots
@@ -115,22 +115,24 @@ struct Fast {
 #pragma unroll
     for (int s = 0; s < B; ++s) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) tl.x[s][c] = bload<TS>(rx, lx + (uint32_t)((s * Ctot + c0 + c) * S) * ES);
-      tl.w[s] = __builtin_amdgcn_raw_buffer_load_b8(rw, lw + (uint32_t)(s * S), 0, 0);
+      for (int c = 0; c < C; ++c)
+        tl.x[s][c] = bload<TS, SWEEP2 ? kStream : kKeep>(rx, lx + (uint32_t)((s * Ctot + c0 + c) * S) * ES);
+      tl.w[s] = __builtin_amdgcn_raw_buffer_load_b8(rw, lw + (uint32_t)(s * S), 0, SWEEP2 ? kStream : kKeep);
     }
     if constexpr (PERDIFF) {
       const int rl = rows_from(t0, T - D);
       const int tl0 = rl > 0 ? t0 : 0;
       const auto rlm = make_rsrc(lb + (int64_t)tl0 * S, rl * S * ES);
 #pragma unroll
-      for (int s = 0; s < B; ++s) tl.lam[s] = bload<TS>(rlm, lx + (uint32_t)(s * S) * ES);
+      for (int s = 0; s < B; ++s) tl.lam[s] = bload<TS, SWEEP2 ? kStream : kKeep>(rlm, lx + (uint32_t)(s * S) * ES);
     }
     if constexpr (BWD && SWEEP2) {
       const auto rz = make_rsrc(zb + (int64_t)tb * Ctot * S, rows * Rx);
 #pragma unroll
       for (int s = 0; s < B; ++s)
 #pragma unroll
-        for (int c = 0; c < C; ++c) tl.z[s][c] = bload<TS>(rz, lx + (uint32_t)((s * Ctot + c0 + c) * S) * ES);
+        for (int c = 0; c < C; ++c)
+          tl.z[s][c] = bload<TS, kStream>(rz, lx + (uint32_t)((s * Ctot + c0 + c) * S) * ES);
     }
   }
 
@@ -188,15 +190,15 @@ struct Fast {
     int f = 0;
     const uint32_t base = lc + (uint32_t)(j * NF) * S * 8u;
 #pragma unroll
-    for (int jj = 1; jj <= D; ++jj) bstore<double>(r, base + (uint32_t)(f++ * S * 8), st.invD[jj]);
+    for (int jj = 1; jj <= D; ++jj) bstore<double, kStream>(r, base + (uint32_t)(f++ * S * 8), st.invD[jj]);
 #pragma unroll
     for (int jj = 1; jj < D; ++jj)
 #pragma unroll
-      for (int k = 1; k <= D - jj; ++k) bstore<double>(r, base + (uint32_t)(f++ * S * 8), st.R[jj][k]);
+      for (int k = 1; k <= D - jj; ++k) bstore<double, kStream>(r, base + (uint32_t)(f++ * S * 8), st.R[jj][k]);
 #pragma unroll
     for (int jj = 1; jj <= D; ++jj)
 #pragma unroll
-      for (int c = 0; c < C; ++c) bstore<double>(r, base + (uint32_t)(f++ * S * 8), st.y[jj][c]);
+      for (int c = 0; c < C; ++c) bstore<double, kStream>(r, base + (uint32_t)(f++ * S * 8), st.y[jj][c]);
   }
 
   // checkpoint of tile j plus the weight window lambda_{t0-1..t0-D};
@@ -206,7 +208,7 @@ struct Fast {
     const int jc = (j >= 0 && j < nt) ? j : 0;
     const uint32_t base = lc + (uint32_t)(jc * NF) * S * 8u;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) ckv[f] = bload<double>(r, base + (uint32_t)(f * S * 8));
+    for (int f = 0; f < NF; ++f) ckv[f] = bload<double, kStream>(r, base + (uint32_t)(f * S * 8));
     const int t0 = j * B;
     lwin[0] = 0.0;
     if constexpr (PERDIFF) {
@@ -306,13 +308,13 @@ struct Fast {
       if constexpr (!BWD) {
 #pragma unroll
         for (int c = 0; c < C; ++c)
-          bstore<TS>(ro, lx + (uint32_t)((s * Ctot + c0 + c) * S) * ES, from_f64<TS>(failed ? qnan : zt[c]));
+          bstore<TS, kStream>(ro, lx + (uint32_t)((s * Ctot + c0 + c) * S) * ES, from_f64<TS>(failed ? qnan : zt[c]));
       } else {
         const bool obs = tl.w[s] != 0u;
         if (ob) {
 #pragma unroll
           for (int c = 0; c < C; ++c)
-            bstore<TS>(ro, lx + (uint32_t)((s * Ctot + c0 + c) * S) * ES,
+            bstore<TS, kStream>(ro, lx + (uint32_t)((s * Ctot + c0 + c) * S) * ES,
                        from_f64<TS>(failed ? qnan : (obs ? zt[c] : 0.0)));
         }
         double zin[C];
@@ -341,7 +343,7 @@ struct Fast {
           if (gb) {
             const uint32_t o = lx + (uint32_t)(s * S) * ES;
             const double prev = accum ? to_f64(bload<TS>(rg, o)) : 0.0;
-            bstore<TS>(rg, o, from_f64<TS>(failed ? qnan : prev + gt));
+            bstore<TS, kStream>(rg, o, from_f64<TS>(failed ? qnan : prev + gt));
           }
         } else {
           gsum += (FULL || t < T - D) ? gt : 0.0;

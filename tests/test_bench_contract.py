@@ -43,3 +43,33 @@ def test_traffic_is_keyed_to_the_kernel_sources():
         t = bench.measured_traffic(kernel, "heteroscedastic P=65536 T=3288 d=2 C=1")
         stored = rec[f"{kernel}|heteroscedastic P=65536 T=3288 d=2 C=1"]
         assert (t is not None) == (stored["source_hash"] == h)
+
+
+def _fake_rocprof(dirpath, rows):
+    os.makedirs(dirpath, exist_ok=True)
+    with open(os.path.join(dirpath, "1234_counter_collection.csv"), "w") as f:
+        f.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for i, (k, c, v) in enumerate(rows):
+            f.write(f'{i},"{k}",{c},{v}\n')
+
+
+def test_counter_ingest_scales_by_the_copy_calibration(tmp_path, monkeypatch, capsys):
+    solve = "void whs::k_fast<2, 1, 24, float, false, true, false>(whs::FastArgs)"
+    back = "void whs::k_fast<2, 1, 24, float, true, true, false>(whs::FastArgs)"
+    _fake_rocprof(tmp_path / "f", [(solve, "FETCH_SIZE", 1000.0), (solve, "FETCH_SIZE", 3000.0),
+                                   (back, "FETCH_SIZE", 4000.0)])
+    _fake_rocprof(tmp_path / "w", [(solve, "WRITE_SIZE", 500.0), (back, "WRITE_SIZE", 700.0)])
+    _fake_rocprof(tmp_path / "cf", [("void copy_kernel<float>", "FETCH_SIZE", 131072.0)])  # half of 256 MiB
+    _fake_rocprof(tmp_path / "cw", [("void copy_kernel<float>", "WRITE_SIZE", 262144.0)])
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "profiles")
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0123456789abcdef")
+    bench.ingest_counters(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"),
+                          P=65536, T=3288, d=2)
+    rec = json.load(open(tmp_path / "profiles" / "traffic.json"))
+    s = rec["whs_solve|heteroscedastic P=65536 T=3288 d=2 C=1"]
+    assert s["fetch_scale"] == 2.0 and s["write_scale"] == 1.0
+    assert s["read_bytes"] == 2.0 * 2000.0 * 1024 and s["write_bytes"] == 500.0 * 1024
+    b = rec["whs_backward|heteroscedastic P=65536 T=3288 d=2 C=1"]
+    assert b["bytes_per_launch"] == 2.0 * 4000.0 * 1024 + 700.0 * 1024
+    assert s["source_hash"] == "0123456789abcdef"
