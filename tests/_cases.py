@@ -109,3 +109,41 @@ def assert_solution(z, zref, x, w, lam, d, f64: bool, info=None, coef=None):
         be = R.backward_error(x[ok], w[ok], np.asarray(lam)[ok], d, z[ok], coef)
         assert be.max() <= 1e-6, be.max()
     return err
+
+
+def backward_error_interleaved(x, w, lam, z, d, chunk_blocks=256):
+    """Componentwise backward error ``max_t |Omega z - W x|_t / (|Omega||z| + |W x|)_t``
+    of every series of an interleaved batch, on the tensors' own device in float64
+    (plain torch elementwise operations from the definition, daily grid):
+    ``Omega z = W z + D^T (lambda * (D z))``, and with lambda >= 0 every band entry of
+    Omega is a sum of terms of one sign, so ``|Omega| = W + |D|^T Lambda |D|``.
+    x, z: (nb, T, C, S); w: (nb, T, S) uint8; lam: (nb, T-d, S) or (P,).
+    Returns float64 (nb*S,) on the host; padding slots of the last block read 0."""
+    nb, T, C, S = x.shape
+    c = torch.tensor(R.diff_coeffs(d), dtype=torch.float64, device=x.device)
+    out = []
+    for b0 in range(0, nb, chunk_blocks):
+        sl = slice(b0, min(nb, b0 + chunk_blocks))
+        xs = x[sl].double()
+        zs = z[sl].double()
+        ws = (w[sl] != 0).double()[:, :, None, :]
+        if lam.dim() == 1:
+            ln = lam.double()
+            ln = torch.nn.functional.pad(ln, (0, nb * S - ln.numel()))
+            ls = ln.view(nb, 1, 1, S)[sl].expand(-1, T - d, 1, S)
+        else:
+            ls = lam[sl].double()[:, :, None, :]
+        b = ws * xs
+        dz = sum(c[j] * zs[:, j:T - d + j] for j in range(d + 1))
+        adz = sum(abs(c[j]) * zs[:, j:T - d + j].abs() for j in range(d + 1))
+        v, av = ls * dz, ls * adz
+        om_z = ws * zs
+        aom_z = ws * zs.abs()
+        for j in range(d + 1):
+            om_z[:, j:T - d + j] += c[j] * v
+            aom_z[:, j:T - d + j] += abs(c[j]) * av
+        num = (om_z - b).abs()
+        den = aom_z + b.abs()
+        q = torch.where(den > 0, num / den, torch.zeros_like(num))
+        out.append(q.amax(dim=(1, 2)).reshape(-1))
+    return torch.cat(out).cpu().numpy()

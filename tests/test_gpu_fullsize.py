@@ -1,12 +1,16 @@
 """Parity at the measured sizes, in the launch configuration bench.py times.
 
 The workloads are generated exactly as bench.py generates them; the kernels
-run on the whole batch, and sampled series (spread over the batch, the last
-one included) are checked one by one against the oracle.  FP32 storage:
-per-series error <= 1e-4 and componentwise backward error <= 1e-6 for z,
+run on the whole batch.  Every series of every batch gets the condition-free
+check: componentwise backward error of z <= 1e-6 (FP32 storage) or 1e-13
+(FP64), computed from the definition in float64 on the device.  Sampled series
+(spread over the batch, the last one included) are also checked one by one
+against the oracle: FP32 storage per-series error <= 1e-4, FP64 the solve bar
+of the smaller tests (1e-10, or the bound of the result's own backward error),
 1e-4 relative for the adjoint (grad_lambda 1e-3; for one weight per series,
 1e-4 of the summed magnitudes of its terms) against the oracle's adjoint at the
-kernel's stored z.  Plus the finite-difference check of grad_lambda on
+kernel's stored z; GCV scores within 1e-7 and the chosen weight attaining the
+oracle's minimum.  Plus the finite-difference check of grad_lambda on
 16 pixels of the headline batch (FP64 storage, central differences)."""
 
 import numpy as np
@@ -15,6 +19,7 @@ import torch
 
 from oracle import whs_ref as R
 from paper_2604_00048_amd import synth, whs
+from tests._cases import backward_error_interleaved, solve_bar
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -59,6 +64,11 @@ def test_headline_heteroscedastic_fwd_bwd_sampled():
     egl = np.abs(rows(gl, idx) - gl_ref).max(1) / np.abs(gl_ref).max(1)
     assert egx.max() <= 1e-4, egx.max()
     assert egl.max() <= 1e-3, egl.max()
+    be = backward_error_interleaved(pk.x, pk.w, pk.lam, z, d)[:P]
+    print(f"headline: componentwise backward error over all {P} series: max {be.max():.3e}", flush=True)
+    assert be.max() <= 1e-6, be.max()
+    del pk, z, g, gx, gl, ws
+    torch.cuda.empty_cache()
 
 
 def test_headline_grad_lambda_by_finite_differences_on_16_pixels():
@@ -127,7 +137,66 @@ def test_ten_band_fwd_bwd_sampled():
     terms = (np.abs(R.apply_D(u, d)) * np.abs(R.apply_D(zs, d))).sum(axis=(1, 2))
     egl = np.abs(gl[idx].double().cpu().numpy() - gl_ref) / terms
     assert egl.max() <= 1e-4, egl.max()
-    del pk, z, g, gx, ws
+    del g, gx, ws
+    torch.cuda.empty_cache()
+    be = backward_error_interleaved(pk.x, pk.w, pk.lam, z, d, chunk_blocks=64)[:P]
+    print(f"ten bands FP32: componentwise backward error over all {P} series: max {be.max():.3e}", flush=True)
+    assert be.max() <= 1e-6, be.max()
+    del pk, z
+    torch.cuda.empty_cache()
+
+
+def test_ten_band_fp64_forward_full_size():
+    # the FP64 ten-band forward as bench.py --workload multiband --dtype f64 runs it
+    P, T, d, C = 262144, 3288, 2, 10
+    pk = synth.generate_packed("multiband", P, S=64, dtype=torch.float64, device=DEV, chunk=8192, T=T, C=C)
+    desc = whs.make_desc(P, T, d, C, 64, whs.WHS_F64, whs.WHS_LAMBDA_SCALAR)
+    ws = torch.empty(whs.workspace_bytes(desc), dtype=torch.uint8, device=DEV)
+    z, info = whs.whs_solve(pk.x, pk.w, pk.lam, d, P, workspace=ws)
+    torch.cuda.synchronize()
+    del ws
+    torch.cuda.empty_cache()
+    assert int((info != 0).sum()) == 0
+    idx = sample(P, 12)
+    x = series(pk.x, idx)
+    w = rows(pk.w, idx)
+    lam = pk.lam[idx].double().cpu().numpy()
+    zs = series(z, idx)
+    zref, iref = R.solve_band(x, w, lam, d)
+    assert (iref == 0).all()
+    fail, err, allow = solve_bar(zs, zref, x, w, lam, d, 1e-10)
+    print(f"ten bands FP64, sampled: max error {R.rel_err(zs, zref).max():.3e}", flush=True)
+    assert fail.size == 0, (fail, err, allow)
+    be = backward_error_interleaved(pk.x, pk.w, pk.lam, z, d, chunk_blocks=32)[:P]
+    print(f"ten bands FP64: componentwise backward error over all {P} series: max {be.max():.3e}", flush=True)
+    assert be.max() <= 1e-13, be.max()
+    del pk, z
+    torch.cuda.empty_cache()
+
+
+def test_gcv_full_size_sampled():
+    # the plain form's per-series GCV choice over the 21-value grid on 65,536 series
+    # of T = 3288 days (the judge arm of the learned form), scores of sampled series
+    # against the oracle
+    P, T, d = 65536, 3288, 2
+    pk = synth.generate_packed("multiband", P, S=64, dtype=torch.float32, device=DEV, chunk=8192, T=T, C=1)
+    grid = R.gcv_grid()
+    lb, sc, info = whs.whs_gcv(pk.x, pk.w, torch.tensor(grid, device=DEV), d, P, want_scores=True)
+    torch.cuda.synchronize()
+    assert int((info != 0).sum()) == 0
+    idx = sample(P, 8)
+    x = series(pk.x, idx)[:, :, 0]
+    w = rows(pk.w, idx)
+    ref, _, _ = R.gcv_scores(x, w, grid, d)
+    got = sc[idx].cpu().numpy()
+    rel = np.abs(got - ref) / np.abs(ref)
+    print(f"GCV at T = {T}: max relative score error on {len(idx)} series {rel.max():.3e}", flush=True)
+    assert rel.max() < 1e-7, rel.max()
+    pick = np.array([np.argmin(r) for r in got])
+    assert (ref[np.arange(len(idx)), pick] <= ref.min(axis=1) * (1 + 1e-9)).all()
+    np.testing.assert_array_equal(lb[idx].cpu().double().numpy(), torch.tensor(grid[pick]).float().double().numpy())
+    del pk, lb, sc
+    torch.cuda.empty_cache()
 
 
 def test_uneven_batch_plan_sampled():
@@ -140,6 +209,7 @@ def test_uneven_batch_plan_sampled():
     plan.graph_launch(w, lam, x, z, info)
     torch.cuda.synchronize()
     assert int((info != 0).sum()) == 0
+    worst = 0.0
     for dd in descs:
         n, T, d = dd["n_series"], dd["T"], dd["d"]
         pick = sample(n, 3)
@@ -153,4 +223,11 @@ def test_uneven_batch_plan_sampled():
         assert (iref == 0).all()
         assert R.rel_err(zs, zref).max() <= 1e-4, (T, d)
         assert R.backward_error(xs, ws_, ls, d, zs).max() <= 1e-6, (T, d)
+        # every series of the group: condition-free check from the definition
+        xg = x[dd["x_off"]:dd["x_off"] + nb * T * 64].view(nb, T, 1, 64)
+        zg = z[dd["x_off"]:dd["x_off"] + nb * T * 64].view(nb, T, 1, 64)
+        be = backward_error_interleaved(xg, wg, lam[dd["lam_off"]:dd["lam_off"] + n], zg, d)[:n]
+        worst = max(worst, float(be.max()))
+        assert be.max() <= 1e-6, (T, d, be.max())
+    print(f"uneven batch: componentwise backward error over all {N} series: max {worst:.3e}", flush=True)
     plan.close()

@@ -813,3 +813,23 @@ def test_refined_inverse_diagonal_matches_exact_rational_inverse(d):
     err = np.abs(var[0] - ex).max() / np.abs(ex).max()
     bound = R.inverse_diag_error_bound(wa, la, d, 1e-15)[0]
     assert err <= bound, (err, bound)
+
+
+@pytest.mark.parametrize("d,per_diff,C", [(1, True, 1), (2, True, 1), (2, False, 3), (3, True, 2), (4, False, 1)])
+def test_whole_batch_backward_error_helper_matches_the_oracle(d, per_diff, C):
+    # the device-side helper the full-size GPU tests use, run here on the CPU
+    import torch
+    from paper_2604_00048_amd import synth
+    from tests._cases import backward_error_interleaved
+    P, T = 150, 61
+    x, w, lam = _rand_case(P, T, d, p_obs=0.4, per_diff=per_diff, C=C, seed=d)
+    z, _ = R.solve_band(x, w, lam, d)
+    z = z.reshape(P, T, C) * (1 + 1e-9 * np.random.default_rng(0).standard_normal((P, T, C)))
+    ref = R.backward_error(x.reshape(P, T, C), w, lam, d, z)
+    xt = synth.pack_series(torch.tensor(x.reshape(P, T, C)), 64)
+    zt = synth.pack_series(torch.tensor(z), 64)
+    wt = synth.pack_rows(torch.tensor(w), 64)
+    lt = synth.pack_rows(torch.tensor(lam), 64) if per_diff else torch.tensor(lam)
+    got = backward_error_interleaved(xt, wt, lt, zt, d, chunk_blocks=2)[:P]
+    np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-18)
+    assert got.max() > 1e-12  # the perturbation is seen
