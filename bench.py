@@ -496,6 +496,7 @@ def bench_hetero(args):
     median_ms = step_ms[K // 2] if K % 2 else 0.5 * (step_ms[K // 2 - 1] + step_ms[K // 2])
     n_fail = int((info != 0).sum().item())
 
+    print(f"# timed {K} steps: {total_ms / K:.3f} ms per step", file=sys.stderr, flush=True)
     copy_gbs = copy_ceiling(dev)
     fb, bb = alg_bytes(T, d, 1, 4, True)
     bwd_gbs = bb * P / (bwd_ms * 1e-3) / 1e9
@@ -572,7 +573,8 @@ def heldout_clause(dev, steps: int, n_series: int):
     import torch
     from paper_2604_00048_amd import learned
     t0 = time.perf_counter()
-    L = learned.train(dev, steps=steps, batch_size=4096, lr=1e-3)
+    L = learned.train(dev, steps=steps, batch_size=4096, lr=1e-3,
+                      log=lambda m: print("# heldout " + m, file=sys.stderr, flush=True))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     ev = learned.evaluate(L, dev, n_series=n_series, chunk=min(n_series, 65536))
