@@ -261,12 +261,26 @@ int whs_variance(const whs_desc* desc, const uint8_t* w, const void* lambda, voi
  * arguments updated on later calls).  whs_plan_autotune times the candidate
  * configurations (tile-depth profile 0/1/2: 8/16/24 steps for order 1, less
  * for higher orders; 1/2/4 wavefronts per workgroup; 1/2 resident
- * wavefronts per SIMD) on the given buffers (z is overwritten) and
- * keeps the fastest; results are cached in the text file named by
- * $WHS_TUNE_CACHE (default $HOME/.cache/whs_tune.txt), keyed by the device
- * and the (T, d, blocks) of every group; force = 1 ignores the cache.  The
- * configuration changes timing only: every choice gives bitwise-identical z.
- * A plan is used by one stream at a time.
+ * wavefronts per SIMD; lanes per series: one, or two for every group at
+ * least split_T long) on the given buffers (z is overwritten) and keeps the
+ * fastest; results are cached in the text file named by $WHS_TUNE_CACHE
+ * (default $HOME/.cache/whs_tune.txt), keyed by the device and the
+ * (T, d, blocks) of every group; force = 1 ignores the cache.
+ * whs_plan_set_config sets a configuration instead (split_T > 0 requires
+ * waves_per_block == 2; WHS_ERR_ARG otherwise).
+ *
+ * Two lanes per series: the two wavefronts of a workgroup take the same 64
+ * series; one factors rows [0, m+d) in time order, the other rows [m, T) on
+ * the time-reversed series (the same recurrence, Sec. III-A, on reversed w
+ * and lambda), m = (T-d)/2; they meet at the d rows [m, m+d), whose d x d
+ * system both solve, then each back-substitutes its own part.  This halves
+ * the dependent chain of a long series.  It is Cholesky of a symmetric
+ * permutation of Omega, so z differs from the one-lane result by rounding
+ * only; configurations with the same lanes per series give bitwise-identical
+ * z.  info follows the time-order convention in both cases (a failed series
+ * is rescanned in time order).  whs_plan_lanes reports the lanes per series
+ * of a group under the current configuration.  A plan is used by one stream
+ * at a time.
  */
 typedef struct {
   int64_t n_series;  /* series in the group (>= 0)                   */
@@ -292,6 +306,9 @@ int whs_plan_autotune(whs_plan* plan, const uint8_t* w, const void* lambda, cons
  * and number of work items; any pointer may be NULL. */
 int whs_plan_config(const whs_plan* plan, int32_t* tile, int32_t* waves_per_block, int32_t* waves_per_simd,
                     int32_t* n_items);
+int whs_plan_set_config(whs_plan* plan, int32_t tile, int32_t waves_per_block, int32_t waves_per_simd,
+                        int32_t split_T);
+int whs_plan_lanes(const whs_plan* plan, int32_t group, int32_t* lanes_per_series);
 void whs_plan_destroy(whs_plan* plan);
 
 #ifdef __cplusplus

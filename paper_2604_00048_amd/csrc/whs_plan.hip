@@ -7,6 +7,13 @@
 // atomic, so long series start first and short ones fill the tail.  The
 // kernel resets its own queue counters when the last wavefront leaves, so a
 // launch can be replayed from a graph without a memset node.
+//
+// Long series can take two lanes (the autotuner decides per length): the two
+// wavefronts of a workgroup solve the top and the bottom part of the same 64
+// series and meet at a separator of d rows (whs_twist.h), which halves the
+// dependent chain that otherwise sets the batch time.  That kernel serves
+// units of work: one split block (both wavefronts) or two whole blocks (one
+// each).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +29,7 @@
 #include "whs.h"
 #include "whs_fast.h"
 #include "whs_kernels.h"
+#include "whs_twist.h"
 
 namespace whs {
 
@@ -43,6 +51,8 @@ struct PlanArgs {
   int32_t* info;
   double* ck;         // one checkpoint slot per wavefront
   int64_t ck_stride;  // doubles per slot
+  const int4* units;  // two-lane kernel: (kind, item, item, 0); kind 1 = one item split over both wavefronts
+  int n_units;
 };
 
 // tile depth per order for each tuning profile: 0 = (8,8,8,8),
@@ -108,6 +118,129 @@ __global__ __launch_bounds__(256) void k_plan(PlanArgs a) {
   }
 }
 
+// separator exchange between the two wavefronts of a workgroup: per part, the
+// lower triangle of its Schur term and its right-hand side (order d <= 4)
+constexpr int kSepFields = 4 * 5 / 2 + 4;
+
+template <int D>
+__host__ __device__ constexpr int split_point(int T) { return (T - D) / 2; }
+
+template <int D, int B, typename TS, bool PERDIFF>
+__device__ __forceinline__ void twist_item(const PlanArgs& a, const GroupDev& G, int64_t bidx, double* slot,
+                                           int half, double (*sep)[kSepFields][64], int (*flag)[64]) {
+  constexpr int NY = D * (D + 1) / 2;
+  const int lane = threadIdx.x & 63;
+  const int T = G.T;
+  Twist<D, B, TS, PERDIFF> k;
+  k.T = T;
+  k.S = 64;
+  k.m = split_point<D>(T);
+  k.rev = half == 1;
+  k.Tv = k.rev ? T - k.m : k.m + D;
+  k.ntv = (k.Tv + B - 1) / B;
+  k.pad = k.ntv * B - k.Tv;
+  k.Rx = 64u * (uint32_t)sizeof(TS);
+  k.xb = static_cast<const TS*>(a.x) + G.x_off + bidx * T * 64;
+  k.zb = static_cast<TS*>(a.z) + G.x_off + bidx * T * 64;
+  k.wb = a.w + G.w_off + bidx * T * 64;
+  k.lb = PERDIFF ? static_cast<const TS*>(a.lam) + G.lam_off + bidx * (T - D) * 64 : nullptr;
+  k.ckb = slot;
+  const int64_t p = bidx * 64 + lane;
+  const bool live = p < G.n_series;
+  constexpr uint32_t kDead = 0x80000000u;
+  k.lx = live ? (uint32_t)lane * (uint32_t)sizeof(TS) : kDead;
+  k.lw = live ? (uint32_t)lane : kDead;
+  k.lc = live ? (uint32_t)lane * 8u : kDead;
+  k.lam_scalar = (!PERDIFF && live) ? to_f64(static_cast<const TS*>(a.lam)[G.lam_off + p]) : 0.0;
+
+  State<D, 1> st;
+  int nobs = 0;
+  const bool ok = k.sweep1(st, nobs, k.rev ? k.Tv - D : k.Tv);  // S counted once, by the top part
+  SepPart<D> sp;
+  k.separator_part(st, sp);
+#pragma unroll
+  for (int i = 0; i < NY; ++i) sep[half][i][lane] = sp.Y[i];
+#pragma unroll
+  for (int r = 0; r < D; ++r) sep[half][NY + r][lane] = sp.c[r];
+  flag[half][lane] = (ok ? 1 : 0) | (nobs << 1);
+  __syncthreads();
+  const int o = 1 - half;
+  double A[NY], rhs[D], Om[NY], bS[D];
+  k.separator_omega(Om, bS);
+#pragma unroll
+  for (int i = 0; i < NY; ++i) A[i] = (sp.Y[i] + sep[o][i][lane]) - Om[i];
+#pragma unroll
+  for (int r = 0; r < D; ++r) rhs[r] = (sp.c[r] + sep[o][NY + r][lane]) - bS[r];
+  const int fo = flag[o][lane];
+  double zS[D];
+  const bool sep_ok = solve_separator<D>(A, rhs, zS);
+  const bool failed = !(ok && (fo & 1) && sep_ok) || nobs + (fo >> 1) < D;
+  if (half == 0 && live && a.info) {
+    int info = 0;
+    if (failed) {
+      info = k.first_bad_pivot();
+      if (info == 0) info = T;  // too few observations, or a separator pivot lost to rounding
+    }
+    a.info[G.info_off + p] = info;
+  }
+  double zSv[D];
+#pragma unroll
+  for (int u = 0; u < D; ++u) zSv[u] = k.rev ? zS[D - 1 - u] : zS[u];
+  k.sweep2(zSv, failed, !k.rev);
+}
+
+template <int PROF, typename TS, bool PERDIFF>
+__device__ __forceinline__ void whole_item(const PlanArgs& a, int item, double* slot) {
+  const int2 it = a.items[item];
+  const GroupDev G = a.groups[it.x];
+  switch (G.d) {
+    case 1: plan_item<1, plan_tile(PROF, 1), TS, PERDIFF>(a, G, it.y, slot); break;
+    case 2: plan_item<2, plan_tile(PROF, 2), TS, PERDIFF>(a, G, it.y, slot); break;
+    case 3: plan_item<3, plan_tile(PROF, 3), TS, PERDIFF>(a, G, it.y, slot); break;
+    default: plan_item<4, plan_tile(PROF, 4), TS, PERDIFF>(a, G, it.y, slot); break;
+  }
+}
+
+// Two wavefronts per workgroup; a.n_waves counts workgroups here.
+template <int PROF, typename TS, bool PERDIFF>
+__global__ __launch_bounds__(128) void k_plan2(PlanArgs a) {
+  __shared__ int s_unit[2];
+  __shared__ double s_sep[2][kSepFields][64];
+  __shared__ int s_flag[2][64];
+  const int half = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double* slot = a.ck + ((int64_t)blockIdx.x * 2 + half) * a.ck_stride;
+  for (int round = 0;; ++round) {
+    // the unit slot alternates: a wavefront still reading last round's slot
+    // cannot see it overwritten before the next barrier
+    if (threadIdx.x == 0) s_unit[round & 1] = atomicAdd(&a.queue[0], 1);
+    __syncthreads();
+    const int u = s_unit[round & 1];
+    if (u >= a.n_units) break;
+    const int4 U = a.units[u];
+    if (U.x == 0) {
+      const int item = half == 0 ? U.y : U.z;
+      if (item >= 0) whole_item<PROF, TS, PERDIFF>(a, item, slot);
+    } else {
+      const int2 it = a.items[U.y];
+      const GroupDev G = a.groups[it.x];
+      switch (G.d) {
+        case 1: twist_item<1, plan_tile(PROF, 1), TS, PERDIFF>(a, G, it.y, slot, half, s_sep, s_flag); break;
+        case 2: twist_item<2, plan_tile(PROF, 2), TS, PERDIFF>(a, G, it.y, slot, half, s_sep, s_flag); break;
+        case 3: twist_item<3, plan_tile(PROF, 3), TS, PERDIFF>(a, G, it.y, slot, half, s_sep, s_flag); break;
+        default: twist_item<4, plan_tile(PROF, 4), TS, PERDIFF>(a, G, it.y, slot, half, s_sep, s_flag); break;
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int done = atomicAdd(&a.queue[1], 1);
+    if (done == a.n_waves - 1) {
+      atomicExch(&a.queue[0], 0);
+      atomicExch(&a.queue[1], 0);
+    }
+  }
+}
+
 }  // namespace whs
 
 // ---------------------------------------------------------------------------
@@ -125,11 +258,28 @@ struct Config {
   int tile = 1;            // tile profile (see plan_tile)
   int waves_per_block = 4;
   int waves_per_simd = 1;  // resident wavefronts per SIMD of the persistent grid
+  int split_T = 0;         // series of at least this length take two lanes (0: none); two-wavefront blocks
 };
 
 template <int PROF, typename TS, bool PD>
 const void* kernel_ptr() {
   return reinterpret_cast<const void*>(&whs::k_plan<PROF, TS, PD>);
+}
+
+template <int PROF, typename TS, bool PD>
+const void* kernel2_ptr() {
+  return reinterpret_cast<const void*>(&whs::k_plan2<PROF, TS, PD>);
+}
+
+const void* pick_kernel2(int prof, bool f64, bool pd) {
+  switch (prof) {
+    case 0: return f64 ? (pd ? kernel2_ptr<0, double, true>() : kernel2_ptr<0, double, false>())
+                       : (pd ? kernel2_ptr<0, float, true>() : kernel2_ptr<0, float, false>());
+    case 2: return f64 ? (pd ? kernel2_ptr<2, double, true>() : kernel2_ptr<2, double, false>())
+                       : (pd ? kernel2_ptr<2, float, true>() : kernel2_ptr<2, float, false>());
+    default: return f64 ? (pd ? kernel2_ptr<1, double, true>() : kernel2_ptr<1, double, false>())
+                        : (pd ? kernel2_ptr<1, float, true>() : kernel2_ptr<1, float, false>());
+  }
 }
 
 const void* pick_kernel(int prof, bool f64, bool pd) {
@@ -163,6 +313,11 @@ struct whs_plan {
   GroupDev* d_groups = nullptr;
   int2* d_items = nullptr;
   int n_items = 0;
+  std::vector<int64_t> item_cost;  // per item, with its group
+  std::vector<int> item_group;
+  int4* d_units = nullptr;         // units of the two-lane kernel for cfg.split_T
+  int n_units = 0;
+  int units_split_T = -1;          // split_T the units were built for
   int* d_queue = nullptr;
   double* d_ck = nullptr;
   size_t ck_capacity = 0;  // doubles
@@ -178,23 +333,81 @@ struct whs_plan {
 
 namespace {
 
+int split_point_d(int d, int T) {
+  switch (d) {
+    case 1: return whs::split_point<1>(T);
+    case 2: return whs::split_point<2>(T);
+    case 3: return whs::split_point<3>(T);
+    default: return whs::split_point<4>(T);
+  }
+}
+
+// a group is split when the configuration asks for it and both parts keep a
+// few tiles of interior
+bool group_split(const whs_group& g, int split_T) { return split_T > 0 && g.T >= split_T && g.T >= 64; }
+
 int64_t max_ck_doubles(const whs_plan* pl, int prof) {
   int64_t mx = 0;
   for (const auto& g : pl->host_groups) {
     const int B = whs::plan_tile(prof, g.d);
-    const int64_t nt = (g.T + B - 1) / B;
+    int64_t nt = (g.T + B - 1) / B;
+    const int m = split_point_d(g.d, g.T);
+    nt = std::max<int64_t>(nt, std::max<int64_t>((m + g.d + B - 1) / B, (g.T - m + B - 1) / B));
     mx = std::max<int64_t>(mx, nt * ck_fields_d(g.d) * 64);
   }
   return mx;
 }
 
+bool two_lane(const Config& c) { return c.split_T > 0; }
+
+// resident wavefronts of the persistent grid (both kernels), a multiple of the
+// wavefronts per workgroup
 int grid_waves(const whs_plan* pl, const Config& c) {
   const int waves = pl->n_cu * 4 * c.waves_per_simd;
-  const int per_block = c.waves_per_block;
-  return std::max(per_block, std::min(waves, ((pl->n_items + per_block - 1) / per_block) * per_block));
+  const int per_block = two_lane(c) ? 2 : c.waves_per_block;
+  const int work = two_lane(c) ? 2 * pl->n_units : pl->n_items;
+  return std::max(per_block, std::min(waves / per_block * per_block, ((work + per_block - 1) / per_block) * per_block));
+}
+
+// Units of the two-lane kernel: split blocks alone, whole blocks in pairs,
+// in order of decreasing cost per wavefront (longest processing time first).
+int build_units(whs_plan* pl, int split_T) {
+  if (pl->units_split_T == split_T) return WHS_OK;
+  std::vector<std::pair<int64_t, int>> pieces;  // (cost per wavefront, item; negative = split)
+  for (int i = 0; i < pl->n_items; ++i) {
+    const whs_group& g = pl->host_groups[pl->item_group[i]];
+    if (group_split(g, split_T))
+      pieces.push_back({pl->item_cost[i] / 2 + 1, -(i + 1)});
+    else
+      pieces.push_back({pl->item_cost[i], i});
+  }
+  std::stable_sort(pieces.begin(), pieces.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  std::vector<int4> units;
+  int pending = -1;
+  for (const auto& pc : pieces) {
+    if (pc.second < 0) {
+      units.push_back(int4{1, -pc.second - 1, -1, 0});
+    } else if (pending < 0) {
+      pending = pc.second;
+    } else {
+      units.push_back(int4{0, pending, pc.second, 0});
+      pending = -1;
+    }
+  }
+  if (pending >= 0) units.push_back(int4{0, pending, -1, 0});
+  if (pl->d_units) hipFree(pl->d_units);
+  pl->d_units = nullptr;
+  pl->n_units = (int)units.size();
+  if (hipMalloc(&pl->d_units, sizeof(int4) * std::max<size_t>(units.size(), 1)) != hipSuccess) return WHS_ERR_HIP;
+  if (!units.empty() &&
+      hipMemcpy(pl->d_units, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return WHS_ERR_HIP;
+  pl->units_split_T = split_T;
+  return WHS_OK;
 }
 
 int ensure_ck(whs_plan* pl, const Config& c) {
+  if (two_lane(c) && build_units(pl, c.split_T) != WHS_OK) return WHS_ERR_HIP;
   const size_t need = (size_t)grid_waves(pl, c) * (size_t)max_ck_doubles(pl, c.tile);
   if (need <= pl->ck_capacity) return WHS_OK;
   if (pl->d_ck) hipFree(pl->d_ck);
@@ -220,15 +433,22 @@ PlanArgs make_args(whs_plan* pl, const Config& c, const uint8_t* w, const void* 
   a.info = info;
   a.ck = pl->d_ck;
   a.ck_stride = max_ck_doubles(pl, c.tile);
+  a.units = pl->d_units;
+  a.n_units = pl->n_units;
+  if (two_lane(c)) a.n_waves /= 2;  // the two-lane kernel counts workgroups
   return a;
 }
 
+const void* kernel_for(const whs_plan* pl, const Config& c) {
+  return two_lane(c) ? pick_kernel2(c.tile, pl->f64, pl->perdiff) : pick_kernel(c.tile, pl->f64, pl->perdiff);
+}
+
+dim3 grid_for(const Config& c, const PlanArgs& a) { return dim3(two_lane(c) ? a.n_waves : a.n_waves / c.waves_per_block); }
+dim3 block_for(const Config& c) { return dim3(two_lane(c) ? 128 : 64 * c.waves_per_block); }
+
 int launch(whs_plan* pl, const Config& c, const PlanArgs& a, hipStream_t stream) {
-  const int threads = 64 * c.waves_per_block;
-  const int blocks = a.n_waves / c.waves_per_block;
   void* args[] = {const_cast<PlanArgs*>(&a)};
-  hipError_t e = hipLaunchKernel(pick_kernel(c.tile, pl->f64, pl->perdiff), dim3(blocks), dim3(threads), args, 0,
-                                 stream);
+  hipError_t e = hipLaunchKernel(kernel_for(pl, c), grid_for(c, a), block_for(c), args, 0, stream);
   return e == hipSuccess ? WHS_OK : WHS_ERR_HIP;
 }
 
@@ -245,11 +465,13 @@ bool cache_lookup(const std::string& key, Config& c) {
   bool found = false;
   while (std::fgets(line, sizeof line, f)) {
     char k[3900];
-    int b, wpb, m;
-    if (std::sscanf(line, "%3899s %d %d %d", k, &b, &wpb, &m) == 4 && key == k) {
+    int b, wpb, m, sp = 0;
+    const int n = std::sscanf(line, "%3899s %d %d %d %d", k, &b, &wpb, &m, &sp);
+    if (n >= 4 && key == k) {
       c.tile = b;
       c.waves_per_block = wpb;
       c.waves_per_simd = m;
+      c.split_T = n == 5 ? sp : 0;
       found = true;
     }
   }
@@ -263,7 +485,7 @@ void cache_store(const std::string& key, const Config& c) {
   if (slash != std::string::npos) mkdir(path.substr(0, slash).c_str(), 0755);  // best effort
   FILE* f = std::fopen(path.c_str(), "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d\n", key.c_str(), c.tile, c.waves_per_block, c.waves_per_simd);
+  std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), c.tile, c.waves_per_block, c.waves_per_simd, c.split_T);
   std::fclose(f);
 }
 
@@ -304,6 +526,10 @@ int whs_plan_create(whs_plan** out, const whs_group* groups, int32_t n_groups, i
   pl->perdiff = lambda_kind == WHS_LAMBDA_PER_DIFF;
   pl->host_groups.assign(groups, groups + n_groups);
   pl->n_items = (int)items.size();
+  for (const auto& it : items) {
+    pl->item_cost.push_back(it.first);
+    pl->item_group.push_back(it.second.x);
+  }
   hipGetDevice(&pl->device);
   hipDeviceGetAttribute(&pl->n_cu, hipDeviceAttributeMultiprocessorCount, pl->device);
   if (pl->n_cu <= 0) pl->n_cu = 256;
@@ -343,6 +569,7 @@ void whs_plan_destroy(whs_plan* pl) {
   if (pl->d_items) hipFree(pl->d_items);
   if (pl->d_queue) hipFree(pl->d_queue);
   if (pl->d_ck) hipFree(pl->d_ck);
+  if (pl->d_units) hipFree(pl->d_units);
   delete pl;
 }
 
@@ -362,9 +589,9 @@ int whs_plan_graph_launch(whs_plan* pl, const uint8_t* w, const void* lambda, co
   if (pl->n_items == 0) return WHS_OK;
   const PlanArgs a = make_args(pl, pl->cfg, w, lambda, x, z, info);
   hipKernelNodeParams kp{};
-  kp.func = const_cast<void*>(pick_kernel(pl->cfg.tile, pl->f64, pl->perdiff));
-  kp.gridDim = dim3(a.n_waves / pl->cfg.waves_per_block);
-  kp.blockDim = dim3(64 * pl->cfg.waves_per_block);
+  kp.func = const_cast<void*>(kernel_for(pl, pl->cfg));
+  kp.gridDim = grid_for(pl->cfg, a);
+  kp.blockDim = block_for(pl->cfg);
   kp.sharedMemBytes = 0;
   pl->graph_args = a;
   void* args[] = {&pl->graph_args};
@@ -395,24 +622,32 @@ int whs_plan_autotune(whs_plan* pl, const uint8_t* w, const void* lambda, const 
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return WHS_ERR_HIP;
   float best = 1e30f;
   Config best_c = pl->cfg;
-  for (int prof : kProfiles) {
-    for (int wpb : {1, 2, 4}) {
-      for (int m : {1, 2}) {
-        Config c{prof, wpb, m};
-        if (ensure_ck(pl, c) != WHS_OK) continue;
-        const PlanArgs a = make_args(pl, c, w, lambda, x, z, nullptr);
-        if (launch(pl, c, a, s) != WHS_OK) continue;  // warm-up
-        hipEventRecord(e0, s);
-        for (int r = 0; r < 3; ++r) launch(pl, c, a, s);
-        hipEventRecord(e1, s);
-        hipEventSynchronize(e1);
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) {
-          best = ms;
-          best_c = c;
-        }
-      }
+  // lanes per series: none split, or every group of at least T split for
+  // each length T within a factor four of the longest
+  std::vector<int> splits{0};
+  int tmax = 0;
+  for (const auto& g : pl->host_groups) tmax = std::max(tmax, g.T);
+  for (const auto& g : pl->host_groups)
+    if (4 * g.T >= tmax && g.T >= 64 && std::find(splits.begin(), splits.end(), g.T) == splits.end())
+      splits.push_back(g.T);
+  std::vector<Config> cands;
+  for (int prof : kProfiles)
+    for (int sp : splits)
+      for (int wpb : sp ? std::vector<int>{2} : std::vector<int>{1, 2, 4})
+        for (int m : {1, 2}) cands.push_back(Config{prof, wpb, m, sp});
+  for (const Config& c : cands) {
+    if (ensure_ck(pl, c) != WHS_OK) continue;
+    const PlanArgs a = make_args(pl, c, w, lambda, x, z, nullptr);
+    if (launch(pl, c, a, s) != WHS_OK) continue;  // warm-up
+    hipEventRecord(e0, s);
+    for (int r = 0; r < 3; ++r) launch(pl, c, a, s);
+    hipEventRecord(e1, s);
+    hipEventSynchronize(e1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      best_c = c;
     }
   }
   hipEventDestroy(e0);
@@ -426,6 +661,31 @@ int whs_plan_autotune(whs_plan* pl, const uint8_t* w, const void* lambda, const 
   }
   cache_store(pl->key, best_c);
   return ensure_ck(pl, best_c);
+}
+
+int whs_plan_set_config(whs_plan* pl, int32_t tile, int32_t waves_per_block, int32_t waves_per_simd,
+                        int32_t split_T) {
+  if (!pl || tile < 0 || tile > 2 || (waves_per_simd != 1 && waves_per_simd != 2) || split_T < 0) return WHS_ERR_ARG;
+  if (split_T > 0 ? waves_per_block != 2 : (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4))
+    return WHS_ERR_ARG;
+  std::lock_guard<std::mutex> lk(pl->mu);
+  const Config c{tile, waves_per_block, waves_per_simd, split_T};
+  const int st = ensure_ck(pl, c);
+  if (st != WHS_OK) return st;
+  pl->cfg = c;
+  if (pl->exec) {  // the graph node must be rebuilt for the new kernel
+    hipGraphExecDestroy(pl->exec);
+    hipGraphDestroy(pl->graph);
+    pl->exec = nullptr;
+    pl->graph = nullptr;
+  }
+  return WHS_OK;
+}
+
+int whs_plan_lanes(const whs_plan* pl, int32_t group, int32_t* lanes_per_series) {
+  if (!pl || !lanes_per_series || group < 0 || group >= (int32_t)pl->host_groups.size()) return WHS_ERR_ARG;
+  *lanes_per_series = group_split(pl->host_groups[group], pl->cfg.split_T) ? 2 : 1;
+  return WHS_OK;
 }
 
 int whs_plan_config(const whs_plan* pl, int32_t* tile, int32_t* waves_per_block, int32_t* waves_per_simd,

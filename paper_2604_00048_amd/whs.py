@@ -85,6 +85,8 @@ SIGNATURES = {
     "whs_plan_autotune": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
     "whs_plan_config": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "whs_plan_set_config": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "whs_plan_lanes": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "whs_plan_destroy": (None, [_VP]),
 }
 
@@ -412,8 +414,19 @@ class Plan:
     def config(self) -> dict:
         v = [ctypes.c_int32() for _ in range(4)]
         _check(lib().whs_plan_config(self._h, *[ctypes.byref(t) for t in v]), "whs_plan_config")
+        lanes = []
+        for g in range(len(self.groups)):
+            n = ctypes.c_int32()
+            _check(lib().whs_plan_lanes(self._h, g, ctypes.byref(n)), "whs_plan_lanes")
+            lanes.append(n.value)
         return {"tile_profile": v[0].value, "waves_per_block": v[1].value, "waves_per_simd": v[2].value,
-                "n_items": v[3].value}
+                "n_items": v[3].value, "lanes_per_series": lanes}
+
+    def set_config(self, tile_profile: int, waves_per_block: int, waves_per_simd: int, split_T: int = 0):
+        """Choose the configuration instead of tuning it (``split_T > 0``: groups of at
+        least that length take two lanes per series, two wavefronts per workgroup)."""
+        _check(lib().whs_plan_set_config(self._h, tile_profile, waves_per_block, waves_per_simd, split_T),
+               "whs_plan_set_config")
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -93,8 +93,10 @@ def inverse_diag_tol(w, lam, d, floor=1e-9, coef=None):
 
 
 def assert_solution(z, zref, x, w, lam, d, f64: bool, info=None, coef=None):
-    """FP64: ``solve_bar`` (1e-10, or the bound the result's own backward error
-    gives on ill-conditioned series); FP32 storage: <= 1e-4.  Always:
+    """``solve_bar`` at 1e-10 (FP64 storage) or 1e-4 (FP32 storage): that error
+    against the oracle, or, on series so ill-conditioned that the FP64 oracle
+    itself is farther than that from the exact solution, the bound the stored
+    result's own backward error gives (its FP32 rounding included).  Always:
     componentwise backward error <= 1e-13 (FP64) / 1e-6 (FP32), which does not
     depend on the conditioning."""
     ok = np.ones(z.shape[0], bool) if info is None else (info == 0)
@@ -105,7 +107,8 @@ def assert_solution(z, zref, x, w, lam, d, f64: bool, info=None, coef=None):
         be = R.backward_error(x[ok], w[ok], np.asarray(lam)[ok], d, z[ok], coef)
         assert be.max() <= 1e-13, be.max()
     else:
-        assert err.max() <= 1e-4, err.max()
+        fail, et, allow = solve_bar(z[ok], zref[ok], x[ok], w[ok], np.asarray(lam)[ok], d, 1e-4, coef)
+        assert fail.size == 0, ("rows", fail, "err", et, "allowed", allow)
         be = R.backward_error(x[ok], w[ok], np.asarray(lam)[ok], d, z[ok], coef)
         assert be.max() <= 1e-6, be.max()
     return err

@@ -199,13 +199,16 @@ def test_gcv_full_size_sampled():
     torch.cuda.empty_cache()
 
 
-def test_uneven_batch_plan_sampled():
+@pytest.mark.parametrize("split_T", [0, 1461])
+def test_uneven_batch_plan_sampled(split_T):
+    # one lane per series, and two for the series of 1461 and 3288 days
     groups = synth.uneven_groups(n_series=100_000, device=DEV)
     x, w, lam, descs = synth.pack_groups(groups, dtype=torch.float32, device=DEV)
     z = torch.empty_like(x)
     N = sum(dd["n_series"] for dd in descs)
     info = torch.full((N,), -1, dtype=torch.int32, device=DEV)
     plan = whs.Plan(descs, torch.float32)
+    plan.set_config(1, 2, 1, split_T)
     plan.graph_launch(w, lam, x, z, info)
     torch.cuda.synchronize()
     assert int((info != 0).sum()) == 0
