@@ -56,10 +56,13 @@ struct PlanArgs {
 };
 
 // tile depth per order for each tuning profile: 0 = (8,8,8,8),
-// 1 = (16,16,8,8), 2 = (24,16,8,8); deeper tiles store fewer checkpoints
-// but hold more registers, which the higher orders cannot afford
-__host__ __device__ constexpr int plan_tile(int prof, int d) {
-  return d >= 3 ? 8 : (prof == 0 ? 8 : (prof == 1 ? 16 : (d == 1 ? 24 : 16)));
+// 1 = (16,16,12,8), 2 = (24,16,16,8), order 3 at most 12 with a weight per
+// difference row; deeper tiles store fewer checkpoints but hold more
+// registers: these are the deepest that compile without spills
+__host__ __device__ constexpr int plan_tile(int prof, int d, bool pd) {
+  return d >= 4 ? 8
+       : d == 3 ? (prof == 0 ? 8 : (prof == 1 || pd) ? 12 : 16)
+                : (prof == 0 ? 8 : (prof == 1 ? 16 : (d == 1 ? 24 : 16)));
 }
 
 template <int D, int B, typename TS, bool PERDIFF>
@@ -101,10 +104,10 @@ __global__ __launch_bounds__(256) void k_plan(PlanArgs a) {
     const int2 it = a.items[item];
     const GroupDev G = a.groups[it.x];
     switch (G.d) {
-      case 1: plan_item<1, plan_tile(PROF, 1), TS, PERDIFF>(a, G, it.y, slot); break;
-      case 2: plan_item<2, plan_tile(PROF, 2), TS, PERDIFF>(a, G, it.y, slot); break;
-      case 3: plan_item<3, plan_tile(PROF, 3), TS, PERDIFF>(a, G, it.y, slot); break;
-      default: plan_item<4, plan_tile(PROF, 4), TS, PERDIFF>(a, G, it.y, slot); break;
+      case 1: plan_item<1, plan_tile(PROF, 1, PERDIFF), TS, PERDIFF>(a, G, it.y, slot); break;
+      case 2: plan_item<2, plan_tile(PROF, 2, PERDIFF), TS, PERDIFF>(a, G, it.y, slot); break;
+      case 3: plan_item<3, plan_tile(PROF, 3, PERDIFF), TS, PERDIFF>(a, G, it.y, slot); break;
+      default: plan_item<4, plan_tile(PROF, 4, PERDIFF), TS, PERDIFF>(a, G, it.y, slot); break;
     }
   }
   // the last wavefront to leave rewinds the queue for the next launch
@@ -194,10 +197,10 @@ __device__ __forceinline__ void whole_item(const PlanArgs& a, int item, double* 
   const int2 it = a.items[item];
   const GroupDev G = a.groups[it.x];
   switch (G.d) {
-    case 1: plan_item<1, plan_tile(PROF, 1), TS, PERDIFF>(a, G, it.y, slot); break;
-    case 2: plan_item<2, plan_tile(PROF, 2), TS, PERDIFF>(a, G, it.y, slot); break;
-    case 3: plan_item<3, plan_tile(PROF, 3), TS, PERDIFF>(a, G, it.y, slot); break;
-    default: plan_item<4, plan_tile(PROF, 4), TS, PERDIFF>(a, G, it.y, slot); break;
+    case 1: plan_item<1, plan_tile(PROF, 1, PERDIFF), TS, PERDIFF>(a, G, it.y, slot); break;
+    case 2: plan_item<2, plan_tile(PROF, 2, PERDIFF), TS, PERDIFF>(a, G, it.y, slot); break;
+    case 3: plan_item<3, plan_tile(PROF, 3, PERDIFF), TS, PERDIFF>(a, G, it.y, slot); break;
+    default: plan_item<4, plan_tile(PROF, 4, PERDIFF), TS, PERDIFF>(a, G, it.y, slot); break;
   }
 }
 
@@ -224,10 +227,10 @@ __global__ __launch_bounds__(128) void k_plan2(PlanArgs a) {
       const int2 it = a.items[U.y];
       const GroupDev G = a.groups[it.x];
       switch (G.d) {
-        case 1: twist_item<1, plan_tile(PROF, 1), TS, PERDIFF>(a, G, it.y, slot, half, s_sep, s_flag); break;
-        case 2: twist_item<2, plan_tile(PROF, 2), TS, PERDIFF>(a, G, it.y, slot, half, s_sep, s_flag); break;
-        case 3: twist_item<3, plan_tile(PROF, 3), TS, PERDIFF>(a, G, it.y, slot, half, s_sep, s_flag); break;
-        default: twist_item<4, plan_tile(PROF, 4), TS, PERDIFF>(a, G, it.y, slot, half, s_sep, s_flag); break;
+        case 1: twist_item<1, plan_tile(PROF, 1, PERDIFF), TS, PERDIFF>(a, G, it.y, slot, half, s_sep, s_flag); break;
+        case 2: twist_item<2, plan_tile(PROF, 2, PERDIFF), TS, PERDIFF>(a, G, it.y, slot, half, s_sep, s_flag); break;
+        case 3: twist_item<3, plan_tile(PROF, 3, PERDIFF), TS, PERDIFF>(a, G, it.y, slot, half, s_sep, s_flag); break;
+        default: twist_item<4, plan_tile(PROF, 4, PERDIFF), TS, PERDIFF>(a, G, it.y, slot, half, s_sep, s_flag); break;
       }
     }
   }
@@ -349,7 +352,7 @@ bool group_split(const whs_group& g, int split_T) { return split_T > 0 && g.T >=
 int64_t max_ck_doubles(const whs_plan* pl, int prof) {
   int64_t mx = 0;
   for (const auto& g : pl->host_groups) {
-    const int B = whs::plan_tile(prof, g.d);
+    const int B = whs::plan_tile(prof, g.d, pl->perdiff);
     int64_t nt = (g.T + B - 1) / B;
     const int m = split_point_d(g.d, g.T);
     nt = std::max<int64_t>(nt, std::max<int64_t>((m + g.d + B - 1) / B, (g.T - m + B - 1) / B));
