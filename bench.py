@@ -27,6 +27,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "series/sec (T=3288,d=2,fwd+bwd) and % of HBM roofline; held-out RMSE vs plain"
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6  # MI355X vector FP64
+# FP64 operations (an FMA counts two) of one step of the GCV kernel's forward
+# recurrence and its derivative along W, per grid value, at d = 1..4
+GCV_FLOPS_PER_STEP = {1: 31, 2: 50, 3: 75, 4: 106}
 
 
 def alg_bytes(T: int, d: int, C: int, esz: int, per_diff: bool):
@@ -282,6 +286,59 @@ def bench_uneven(args):
     }
 
 
+def bench_gcv(args):
+    """The plain form: a scalar weight per series by GCV over 21 grid values
+    (10^-1 .. 10^5), then the solve at the chosen weight."""
+    import torch
+    from paper_2604_00048_amd import synth, whs
+    dev = torch.device("cuda:0")
+    dtype = torch.float64 if args.dtype == "f64" else torch.float32
+    P, T, d, S = args.P, args.T, args.d, args.interleave
+    pk = synth.generate_packed("multiband", P, S=S, dtype=dtype, device=dev, chunk=8192, T=T, C=1)
+    grid = torch.tensor([10.0 ** (-1.0 + 0.3 * i) for i in range(21)], dtype=torch.float64, device=dev)
+    lam_best = torch.empty(P, dtype=dtype, device=dev)
+    info = torch.empty(P, dtype=torch.int32, device=dev)
+    z = torch.empty_like(pk.x)
+    desc = whs.make_desc(P, T, d, 1, S, whs.WHS_F64 if dtype == torch.float64 else whs.WHS_F32, whs.WHS_LAMBDA_SCALAR)
+    ws = torch.empty(whs.workspace_bytes(desc), dtype=torch.uint8, device=dev)
+    ev = _events(2 * args.steps + 2)
+
+    def step(k=None):
+        if k is not None:
+            ev[2 * k].record()
+        whs.whs_gcv(pk.x, pk.w, grid, d, P, lambda_best=lam_best, info=info)
+        if k is not None:
+            ev[2 * k + 1].record()
+        whs.whs_solve(pk.x, pk.w, lam_best, d, P, z=z, workspace=ws)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = ev[-2], ev[-1]
+    e0.record()
+    for k in range(args.steps):
+        step(k)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    gcv_ms = sum(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps)) / args.steps
+    flops = GCV_FLOPS_PER_STEP[d] * T * grid.numel() * P
+    tf = flops / (gcv_ms * 1e-3) / 1e12
+    return {
+        "metric": f"series/sec (GCV over 21 weights + solve, T={T}, d={d})", "value": P / (ms * 1e-3),
+        "unit": "series/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"plain form: GCV choice of a scalar weight over 21 grid values, then the solve at "
+                               f"it: P={P} series, T={T} daily steps, d={d}, one band, "
+                               f"{args.dtype.upper()} storage / FP64 arithmetic",
+                   "P": P, "T": T, "d": d, "n_grid": grid.numel(), "storage": args.dtype},
+        "roofline": {"bound": "alu", "kernel": "whs_gcv", "achieved": tf, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tf / PEAK_FP64_TFLOPS, "traffic": None,
+                     "flops_per_series_step_grid_value": GCV_FLOPS_PER_STEP[d], "ms_per_launch": gcv_ms},
+        "mean_log10_lambda": float(torch.log10(lam_best.double()).mean().item()),
+        "failed_series": int((info != 0).sum().item()),
+    }
+
+
 def bench_learned(args):
     """Learned per-day weights vs the GCV-chosen scalar weight, held-out RMSE and throughput."""
     import torch
@@ -345,7 +402,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="hetero", choices=["hetero", "multiband", "uneven", "learned", "transformer"])
+    ap.add_argument("--workload", default="hetero", choices=["hetero", "multiband", "uneven", "learned", "transformer", "gcv"])
     ap.add_argument("--P", type=int, default=None)
     ap.add_argument("--T", type=int, default=3288)
     ap.add_argument("--d", type=int, default=2, help="difference order of the heteroscedastic workload")
@@ -409,6 +466,10 @@ def main():
         return
     if args.workload == "uneven":
         print(json.dumps(bench_uneven(args)), flush=True)
+        return
+    if args.workload == "gcv":
+        args.P = args.P or 262144
+        print(json.dumps(bench_gcv(args)), flush=True)
         return
     if args.workload == "learned":
         args.eval_series = args.eval_series or 262144

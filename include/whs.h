@@ -171,14 +171,17 @@ int whs_backward(const whs_desc* desc, const uint8_t* w, const void* lambda,
  * series is smoothed (eq. (2)) and scored
  *     GCV_g = m RSS / (m - ED)^2,  m = sum_t w_t,
  *     RSS = sum_t w_t (x_t - z_t)^2,  ED = sum_t w_t (Omega^{-1})_{tt},
- * with diag(Omega^{-1}) from the selected-inverse recurrence on the banded
- * factor.  lambda_best[p] is the grid value of the first minimum (NaN if
- * every grid value failed).  Requires n_rhs == 1, lambda_kind == SCALAR
- * (it describes lambda_best), interleave a multiple of 64
+ * ED and RSS are computed in one forward sweep of the banded factorisation
+ * per grid value, as derivatives along Omega + eps W (ED = d/deps log det,
+ * RSS = sum w x^2 minus d/deps of b^T Omega^{-1} b), equal to the sums above
+ * up to rounding.  lambda_best[p] is the grid value of the first minimum
+ * (NaN if every grid value failed).  Requires n_rhs == 1, lambda_kind ==
+ * SCALAR (it describes lambda_best), interleave a multiple of 64
  * (WHS_ERR_UNSUPPORTED otherwise).  grid: device FP64[n_grid], n_grid >= 1.
  * scores: device FP64[P][n_grid] or NULL.  info: 0 if some grid value
  * succeeded, else the first grid value's failure code.  x is read at w = 1
- * only.  The workspace size is whs_gcv_workspace_bytes(desc).
+ * only.  No workspace is used: whs_gcv_workspace_bytes returns 0 and
+ * workspace may be NULL.
  */
 size_t whs_gcv_workspace_bytes(const whs_desc* desc);
 int whs_gcv(const whs_desc* desc, const uint8_t* w, const void* x, const double* grid, int32_t n_grid,

@@ -518,220 +518,16 @@ __global__ __launch_bounds__(256) void k_fast(FastArgs a) {
 namespace whs {
 
 // ---------------------------------------------------------------------------
-// Generalised cross-validation over a grid of scalar weights.
-//
-// For each grid value the series is factored and solved exactly as in the
-// solve kernel; the reverse sweep additionally runs the selected-inverse
-// recurrence of Sigma = Omega^{-1} from the LDL^T factor,
-//   Sigma[t, t+j] = -sum_i L[t+i, t] Sigma[t+i, t+j]      (j >= 1)
-//   Sigma[t, t]   = 1/Dp[t] - sum_i L[t+i, t] Sigma[t+i, t],
-// carrying the d x d block Sigma[t+1..t+d, t+1..t+d].  It accumulates the
-// effective dimension ED = sum_t w_t Sigma[t, t] and RSS = sum_t w_t (x_t - z_t)^2,
-// scores GCV = m RSS / (m - ED)^2 and keeps the first minimum.
-// ---------------------------------------------------------------------------
-
-struct GcvArgs {
-  int64_t P;
-  int T, S, nt, n_grid;
-  const uint8_t* w;
-  const void* x;
-  const double* grid;
-  void* lam_best;
-  double* scores;
-  int32_t* info;
-  double* ck;
-};
-
-template <int D, int B, typename TS>
-struct Gcv : Fast<D, 1, B, TS, false, false> {
-  using Base = Fast<D, 1, B, TS, false, false>;
-  using typename Base::Tile;
-  static constexpr int NF = Base::NF;
-
-  template <bool FULL>
-  __device__ __forceinline__ void rev_tile_gcv(const Tile& tl, int t0, const double (&ckv)[NF],
-                                               const double (&lwin)[D + 1], double (&zn)[D + 1],
-                                               double (&sg)[D + 1][D + 1], double (&lcr)[D + 1][D + 1],
-                                               double& rss, double& ed) const {
-    State<D, 1> st;
-    this->restore(st, ckv, lwin);
-    double lt[B][D + 1];
-    double yd[B];
-    double id[B];
-#pragma unroll
-    for (int s = 0; s < B; ++s) {
-      const int t = t0 + s;
-      double l[D + 1], dt, invdt, yt[1];
-      this->template step<FULL>(st, tl, s, t, l, dt, invdt, yt);
-      const bool v = FULL || t < this->T;
-#pragma unroll
-      for (int i = 1; i <= D; ++i) lt[s][i] = v ? l[i] : 0.0;
-      yd[s] = v ? yt[0] * invdt : 0.0;
-      id[s] = v ? invdt : 0.0;
-    }
-#pragma unroll
-    for (int s = B - 1; s >= 0; --s) {
-      const int t = t0 + s;
-      double L[D + 1];
-#pragma unroll
-      for (int i = 1; i <= D; ++i)
-        L[i] = (s + i < B) ? lt[s + i < B ? s + i : 0][i] : lcr[s + i - B < 0 ? 0 : s + i - B][i];
-      double zt = yd[s];
-#pragma unroll
-      for (int i = 1; i <= D; ++i) zt = __builtin_fma(-L[i], zn[i], zt);
-      // Sigma[t+j, t], j = 1..D, from the carried block sg[a][b] = Sigma[t+1+a, t+1+b]
-      double sj[D + 1];
-#pragma unroll
-      for (int j = 1; j <= D; ++j) {
-        double acc = 0.0;
-#pragma unroll
-        for (int i = 1; i <= D; ++i) acc = __builtin_fma(-L[i], sg[i - 1][j - 1], acc);
-        sj[j] = acc;
-      }
-      double stt = id[s];
-#pragma unroll
-      for (int i = 1; i <= D; ++i) stt = __builtin_fma(-L[i], sj[i], stt);
-      if (FULL || t < this->T) {
-        const bool obs = tl.w[s] != 0u;
-        const double r = to_f64(tl.x[s][0]) - zt;
-        rss += obs ? r * r : 0.0;
-        ed += obs ? stt : 0.0;
-#pragma unroll
-        for (int a = D - 1; a >= 1; --a)
-#pragma unroll
-          for (int b = D - 1; b >= 1; --b) sg[a][b] = sg[a - 1][b - 1];
-        sg[0][0] = stt;
-#pragma unroll
-        for (int b = 1; b < D; ++b) {
-          sg[0][b] = sj[b];
-          sg[b][0] = sj[b];
-        }
-#pragma unroll
-        for (int i = D; i >= 2; --i) zn[i] = zn[i - 1];
-        zn[1] = zt;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < D; ++r)
-#pragma unroll
-      for (int i = 0; i <= D; ++i) lcr[r][i] = lt[r][i];
-  }
-
-  __device__ void run(const GcvArgs& g) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int wave_off = __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
-    const int64_t p0 = (int64_t)blockIdx.x * blockDim.x + wave_off;
-    if (p0 >= g.P) return;
-    const int64_t bidx = p0 / g.S;
-    const int s_in = (int)(p - bidx * g.S);
-    this->T = g.T;
-    this->S = g.S;
-    this->Ctot = 1;
-    this->c0 = 0;
-    this->nt = g.nt;
-    this->Rx = (uint32_t)g.S * sizeof(TS);
-    this->xb = static_cast<const TS*>(g.x) + bidx * g.T * g.S;
-    this->wb = g.w + bidx * g.T * g.S;
-    this->lb = nullptr;
-    this->zb = nullptr;
-    this->ob = nullptr;
-    this->gb = nullptr;
-    this->ckb = g.ck + bidx * g.nt * NF * g.S;
-    this->accum = false;
-    const bool live = p < g.P;
-    constexpr uint32_t kDead = 0x80000000u;
-    this->lx = live ? (uint32_t)s_in * (uint32_t)sizeof(TS) : kDead;
-    this->lw = live ? (uint32_t)s_in : kDead;
-    this->lc = live ? (uint32_t)s_in * 8u : kDead;
-    const int T = g.T, nt = g.nt;
-
-    double best = __builtin_huge_val();
-    int best_i = -1;
-    int first_info = 0;
-    for (int gi = 0; gi < g.n_grid; ++gi) {
-      this->lam_scalar = g.grid[gi];
-      // sweep 1
-      State<D, 1> st;
-      st.zero();
-      int nobs = 0, bad_tile = -1;
-      Tile A, Bt;
-      this->template load_tile<false>(A, 0);
-      for (int j = 0; j < nt; j += 2) {
-        this->template load_tile<false>(Bt, (j + 1) * B);
-        this->store_ck(st, j);
-        bool ok = this->full_tile(j * B) ? this->template fwd_tile<true>(st, A, j * B, nobs)
-                                         : this->template fwd_tile<false>(st, A, j * B, nobs);
-        if (!ok && bad_tile < 0) bad_tile = j;
-        this->template load_tile<false>(A, (j + 2) * B);
-        if (j + 1 < nt) {
-          this->store_ck(st, j + 1);
-          ok = this->full_tile((j + 1) * B) ? this->template fwd_tile<true>(st, Bt, (j + 1) * B, nobs)
-                                            : this->template fwd_tile<false>(st, Bt, (j + 1) * B, nobs);
-          if (!ok && bad_tile < 0) bad_tile = j + 1;
-        }
-      }
-      int info = 0;
-      if (live && bad_tile >= 0) info = this->first_bad_pivot((bad_tile + 1) * B);
-      if (info == 0 && nobs < D) info = T;
-      if (gi == 0) first_info = info;
-      // sweep 2
-      double zn[D + 1], sg[D + 1][D + 1], lcr[D + 1][D + 1];
-#pragma unroll
-      for (int i = 0; i <= D; ++i) {
-        zn[i] = 0.0;
-#pragma unroll
-        for (int k = 0; k <= D; ++k) {
-          sg[i][k] = 0.0;
-          lcr[i][k] = 0.0;
-        }
-      }
-      double rss = 0.0, ed = 0.0;
-      double ckA[NF], ckB[NF], lwA[D + 1], lwB[D + 1];
-      int j = nt - 1;
-      this->template load_tile<true>(A, j * B);
-      this->load_ck(j, ckA, lwA);
-      for (; j >= 0; j -= 2) {
-        this->template load_tile<true>(Bt, (j - 1) * B);
-        this->load_ck(j - 1, ckB, lwB);
-        if (this->full_tile(j * B)) rev_tile_gcv<true>(A, j * B, ckA, lwA, zn, sg, lcr, rss, ed);
-        else rev_tile_gcv<false>(A, j * B, ckA, lwA, zn, sg, lcr, rss, ed);
-        this->template load_tile<true>(A, (j - 2) * B);
-        this->load_ck(j - 2, ckA, lwA);
-        if (j - 1 >= 0) {
-          if (this->full_tile((j - 1) * B)) rev_tile_gcv<true>(Bt, (j - 1) * B, ckB, lwB, zn, sg, lcr, rss, ed);
-          else rev_tile_gcv<false>(Bt, (j - 1) * B, ckB, lwB, zn, sg, lcr, rss, ed);
-        }
-      }
-      const double m = (double)nobs;
-      const double den = m - ed;
-      const double score = (info == 0) ? m * rss / (den * den) : __builtin_nan("");
-      if (live && g.scores) g.scores[p * g.n_grid + gi] = score;
-      if (score < best) {  // NaN never wins; the first minimum is kept
-        best = score;
-        best_i = gi;
-      }
-    }
-    if (live) {
-      static_cast<TS*>(g.lam_best)[p] = from_f64<TS>(best_i >= 0 ? g.grid[best_i] : __builtin_nan(""));
-      if (g.info) g.info[p] = best_i >= 0 ? 0 : first_info;
-    }
-  }
-};
-
-template <int D, int B, typename TS>
-__global__ __launch_bounds__(256) void k_gcv(GcvArgs a) {
-  Gcv<D, B, TS> k;
-  k.run(a);
-}
-
-
-// ---------------------------------------------------------------------------
 // Posterior variance: the diagonal of Omega^{-1}.
 //
 // Sweep 1 factors the series (no right-hand side: x reads as zero through an
 // empty buffer range) and checkpoints the state as in the solve kernel; the
-// reverse sweep recomputes each tile and runs the same selected-inverse
-// recurrence as the GCV kernel, storing Sigma[t, t] for every t.
+// reverse sweep recomputes each tile and runs the selected-inverse recurrence
+// of Sigma = Omega^{-1} on the LDL^T factor,
+//   Sigma[t, t+j] = -sum_i L[t+i, t] Sigma[t+i, t+j]      (j >= 1)
+//   Sigma[t, t]   = 1/Dp[t] - sum_i L[t+i, t] Sigma[t+i, t],
+// carrying the d x d block Sigma[t+1..t+d, t+1..t+d] and storing Sigma[t, t]
+// for every t.
 // ---------------------------------------------------------------------------
 
 struct VarArgs {

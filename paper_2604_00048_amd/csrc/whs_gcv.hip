@@ -1,27 +1,16 @@
 // GCV weight selection: launches of the grid-search kernel.
 #include <hip/hip_runtime.h>
 
-#include "whs_fast.h"
+#include "whs_gcv.h"
 #include "whs_kernels.h"
 
 namespace whs {
 
-// tile depth of the GCV kernel (its reverse sweep also keeps 1/Dp per step)
-constexpr int gcv_tile(int D) { return D <= 2 ? 16 : 8; }
-
-size_t gcv_checkpoint_bytes(int64_t P, int S, int T, int D) {
-  const int64_t nb = (P + S - 1) / S;
-  const int64_t nt = (T + gcv_tile(D) - 1) / gcv_tile(D);
-  int nf = 0;
-  switch (D) {
-    case 1: nf = ck_fields<1, 1>(); break;
-    case 2: nf = ck_fields<2, 1>(); break;
-    case 3: nf = ck_fields<3, 1>(); break;
-    case 4: nf = ck_fields<4, 1>(); break;
-    default: return 0;
-  }
-  return (size_t)nb * nt * nf * S * sizeof(double);
-}
+// steps per loaded tile, and the number of grid values that share one pass
+// over the inputs (the most whose recurrences fit in registers without spills:
+// 21 grid values are three passes at order 1 or 2)
+constexpr int gcv_tile(int) { return 8; }
+constexpr int gcv_group(int D) { return D <= 2 ? 7 : (D == 3 ? 3 : 2); }
 
 template <int D, typename TS>
 static hipError_t gcv_t(const GcvLaunch& L, hipStream_t stream) {
@@ -38,10 +27,9 @@ static hipError_t gcv_t(const GcvLaunch& L, hipStream_t stream) {
   a.lam_best = L.lam_best;
   a.scores = L.scores;
   a.info = L.info;
-  a.ck = L.ws;
   const int threads = 256;
   const int64_t blocks = (L.P + threads - 1) / threads;
-  hipLaunchKernelGGL((k_gcv<D, B, TS>), dim3((unsigned)blocks), dim3(threads), 0, stream, a);
+  hipLaunchKernelGGL((k_gcv<D, B, TS, gcv_group(D)>), dim3((unsigned)blocks), dim3(threads), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -48,10 +48,8 @@ struct GcvLaunch {
   void* lam_best;
   double* scores;
   int32_t* info;
-  double* ws;
 };
 
-size_t gcv_checkpoint_bytes(int64_t P, int S, int T, int D);
 hipError_t launch_gcv(const GcvLaunch& L, hipStream_t stream);
 
 }  // namespace whs

@@ -340,9 +340,10 @@ def whs_gcv(x: torch.Tensor, w: torch.Tensor, grid: torch.Tensor, d: int, P: int
     if info is None:
         info = torch.empty(P, dtype=torch.int32, device=x.device)
     n = int(lib().whs_gcv_workspace_bytes(ctypes.byref(desc)))
-    ws = workspace if workspace is not None else torch.empty(max(n, 8), dtype=torch.uint8, device=x.device)
+    ws = workspace if workspace is not None or n == 0 else torch.empty(n, dtype=torch.uint8, device=x.device)
+    nbytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(lib().whs_gcv(ctypes.byref(desc), _ptr(w), _ptr(x), _ptr(grid), int(grid.numel()), _ptr(lambda_best),
-                         _ptr(scores), _ptr(info), _ptr(ws), ws.numel() * ws.element_size(), _stream(x.device)),
+                         _ptr(scores), _ptr(info), _ptr(ws), nbytes, _stream(x.device)),
            "whs_gcv")
     return lambda_best, scores, info
 

@@ -536,6 +536,39 @@ def test_P12_gcv_argmin_matches_closed_form_scan():
     np.testing.assert_array_equal(idx, np.argmin(ref, axis=1))
 
 
+@pytest.mark.parametrize("d,lam", [(1, 5.0), (2, 40.0), (3, 900.0)])
+def test_gcv_sums_are_derivatives_along_the_weights(d, lam):
+    # ED = tr(Omega^{-1} W) = d/deps log det(Omega + eps W) (Jacobi's formula) and
+    # RSS = d/deps min_z [(1+eps) |x - z|_W^2 + lam |D z|^2] (envelope theorem), the
+    # minimum being (1+eps) x'Wx - b'(Omega + eps W)^{-1} b with b = (1+eps) W x.
+    # Central differences of dense LAPACK quantities against the oracle's plain sums.
+    T = 60
+    r = np.random.default_rng(31 + d)
+    w = (r.random((1, T)) < 0.5).astype(np.uint8)
+    w[0, ::7] = 1
+    x = np.where(w != 0, 3.0 + np.sin(np.arange(T) / 5.0) + 0.2 * r.normal(size=(1, T)), 0.0)
+    _, ed, rss = R.gcv_scores(x, w, np.array([lam]), d)
+    Om = R.omega_dense(w, np.array([lam]), d)[0]
+    W = np.diag(w[0].astype(np.float64))
+
+    def logdet(eps):
+        sgn, v = np.linalg.slogdet(Om + eps * W)
+        assert sgn > 0
+        return v
+
+    # x relative to its first observed value: the smoother keeps constants, so RSS is
+    # unchanged, and the two terms of the minimum cancel less
+    xs = np.where(w[0] != 0, x[0] - x[0][np.argmax(w[0] != 0)], 0.0)
+
+    def fmin(eps):
+        b = (1.0 + eps) * (W @ xs)
+        return (1.0 + eps) * xs @ W @ xs - b @ np.linalg.solve(Om + eps * W, b)
+
+    h = 1e-4
+    np.testing.assert_allclose((logdet(h) - logdet(-h)) / (2 * h), ed[0, 0], rtol=1e-7)
+    np.testing.assert_allclose((fmin(h) - fmin(-h)) / (2 * h), rss[0, 0], rtol=1e-6)
+
+
 def test_gcv_grid_and_tie_rule():
     grid = R.gcv_grid()
     assert grid.size == 21
