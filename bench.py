@@ -604,6 +604,7 @@ def bench_hetero(args):
         },
         "failed_series": n_fail,
         "wall_s_timed": wall,
+        "build_id": whs.build_id(),
     }
     if not args.no_cpu_baseline:
         n = min(args.cpu_sample, P)

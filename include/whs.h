@@ -83,6 +83,12 @@ const char* whs_status_str(int status);
 /* Library ABI version (major*10000 + minor*100 + patch). */
 int whs_version(void);
 
+/* Build id: the first 16 hex digits of the SHA-256 of the HIP sources and
+ * headers the library was compiled from (static storage; "unknown" if the
+ * build did not set it).  Lets a caller check that a prebuilt library matches
+ * the sources beside it. */
+const char* whs_build_id(void);
+
 /* Bytes of device workspace whs_solve / whs_backward need for `desc`
  * (inter-sweep checkpoints; 0 when P = 0).  Any 256-byte aligned buffer of
  * at least this size may be passed; its contents need no initialisation and

@@ -7,6 +7,7 @@ Every call recompiles; objects go to ``paper_2604_00048_amd/_build/``.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import shutil
 import subprocess
@@ -31,6 +32,20 @@ FLAGS = [
 ]
 
 
+def source_hash() -> str:
+    """SHA-256 (first 16 hex digits) of every HIP source and header the library is built from."""
+    h = hashlib.sha256()
+    files = []
+    for top in (CSRC, INCLUDE):
+        for dirpath, _, names in os.walk(top):
+            files += [os.path.join(dirpath, f) for f in names if f.endswith((".hip", ".h"))]
+    for f in sorted(files, key=lambda q: os.path.relpath(q, ROOT)):
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def sources() -> list[str]:
     out = []
     for dirpath, _, files in os.walk(CSRC):
@@ -40,10 +55,10 @@ def sources() -> list[str]:
     return sorted(out)
 
 
-def _compile(src: str) -> str:
+def _compile(src: str, build_id: str) -> str:
     rel = os.path.relpath(src, CSRC).replace(os.sep, "_")
     obj = os.path.join(BUILD, rel + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, f"-DWHS_BUILD_ID=\"{build_id}\"", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -54,8 +69,9 @@ def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)), 16)
+    build_id = source_hash()
     with cf.ThreadPoolExecutor(max_workers=max(jobs, 1)) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, build_id), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -63,7 +79,7 @@ def build(verbose: bool = True) -> str:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
     if verbose:
-        print(f"built {LIB} from {len(srcs)} sources", flush=True)
+        print(f"built {LIB} from {len(srcs)} sources, build id {build_id}", flush=True)
     return LIB
 
 

@@ -199,6 +199,11 @@ const char* whs_status_str(int status) {
 
 int whs_version(void) { return 100; }
 
+#ifndef WHS_BUILD_ID
+#define WHS_BUILD_ID "unknown"
+#endif
+const char* whs_build_id(void) { return WHS_BUILD_ID; }
+
 size_t whs_workspace_bytes(const whs_desc* desc) {
   if (check_desc(desc) != WHS_OK || desc->n_series == 0) return 0;
   return whs::checkpoint_bytes(desc->n_series, desc->interleave, desc->T, desc->d, desc->n_rhs);

@@ -21,6 +21,8 @@ import os
 
 import torch
 
+from .build import source_hash
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwhs.so")
 
@@ -63,6 +65,7 @@ _DP = ctypes.POINTER(WhsDesc)
 SIGNATURES = {
     "whs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "whs_version": (ctypes.c_int, []),
+    "whs_build_id": (ctypes.c_char_p, []),
     "whs_workspace_bytes": (_SZ, [_DP]),
     "whs_interleave_workspace_bytes": (_SZ, [_DP]),
     "whs_factor_bytes": (_SZ, [_DP]),
@@ -103,8 +106,18 @@ def lib() -> ctypes.CDLL:
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        built = L.whs_build_id().decode()
+        want = source_hash()
+        if built != want:
+            raise RuntimeError(f"{LIB_PATH} was built from other sources (build id {built}, sources {want}): "
+                               "rebuild it with __graft_entry__.build()")
         _lib = L
     return _lib
+
+
+def build_id() -> str:
+    """Build id of the loaded library (hash of the sources it was compiled from)."""
+    return lib().whs_build_id().decode()
 
 
 def status_str(code: int) -> str:

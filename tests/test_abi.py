@@ -22,6 +22,13 @@ def test_library_built():
     assert os.path.exists(whs.LIB_PATH), "run __graft_entry__.build() first"
 
 
+def test_library_matches_the_sources():
+    # the binding refuses a library built from other sources; the id is the source hash
+    from paper_2604_00048_amd.build import source_hash
+    assert whs.build_id() == source_hash()
+    assert len(whs.build_id()) == 16
+
+
 def test_every_declared_symbol_is_exported():
     from paper_2604_00048_amd import net
     L = whs.lib()
