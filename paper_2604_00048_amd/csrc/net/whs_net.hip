@@ -182,6 +182,210 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
 }
 
 // ---------------------------------------------------------------------------
+// The 64-in, 64-out layers (MODE 0: + bias, ReLU; MODE 2: input gradient,
+// out *= (mask > 0)) as out^T = W . window on v_mfma_f32_32x32x16_bf16.  The
+// weights are the A operand, in registers (lane l: output channel l % 32 of a
+// 32-channel half, K entries 8 (l / 32) .. +7 of each 16-wide K step); the
+// input window is the B operand, read from LDS (lane l: time row l % 32, 8
+// channels).  A wavefront computes 64 time rows x all 64 channels, so each
+// 1 KB LDS read feeds two 32x32x16 products (both channel halves) and four
+// independent accumulators are in flight per K step.  The accumulators of a
+// lane hold 4 consecutive channels of one time row (accumulator j: channel
+// 8 (j / 4) + 4 (l / 32) + j % 4 of its half, time l % 32), which leave as
+// 8-byte stores.  Tile: 256 time rows of one series, 64 per wavefront.
+//
+// Pipelined over the tiles a workgroup walks (blockIdx.x, + gridDim.x, ...):
+// the next tile's input window goes straight from HBM into the other of two
+// LDS buffers (buffer-to-LDS loads; rows outside the series read as zero
+// through the buffer range) while this tile is computed, and a tile's output
+// (staged in LDS) is stored during the first K steps of the next tile, so its
+// LDS reads and stores overlap the products, and the one wait per tile is for
+// memory operations issued a whole tile earlier.  MODE 2 fetches the
+// tile's mask rows the same way and applies them when the tile is stored.
+// LDS rows are 128 B with the 16-byte chunks of row r permuted by XOR with
+// (r >> 1) & 7, so the 16 rows read by a quarter wavefront hit distinct banks.
+// ---------------------------------------------------------------------------
+constexpr int TR64 = 256;  // time rows per tile of the 64-to-64 layers
+
+template <int MODE>
+__global__ __launch_bounds__(256, 1) void k_conv64(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wt,
+                                                   const float* __restrict__ bias, const uint16_t* __restrict__ mask,
+                                                   uint16_t* __restrict__ out, int T, int ntiles, int64_t total) {
+  constexpr int C = 64;
+  constexpr int ROWS = TR64 + 2 * HALO;   // input window rows (264)
+  constexpr int WB = ROWS * 128;          // bytes of one window buffer
+  constexpr int OS = C + 8;               // output tile row stride in bf16 (144 B)
+  constexpr int NS = KT * C / 16;         // K steps of 16
+  typedef __attribute__((ext_vector_type(16))) float f32x16;
+  typedef __attribute__((ext_vector_type(2))) uint32_t u32x2;
+  typedef __attribute__((address_space(3))) void* lptr;
+  // two window buffers as separate objects, so the compiler can tell the reads
+  // of one from the loads in flight into the other and waits for neither
+  __shared__ __attribute__((aligned(1024))) unsigned char win0[WB];
+  __shared__ __attribute__((aligned(1024))) unsigned char win1[WB];
+  __shared__ __attribute__((aligned(1024))) unsigned char mbuf[MODE == 2 ? TR64 * 128 : 16];
+  __shared__ __attribute__((aligned(16))) uint16_t otile[TR64 * OS];
+  __shared__ float sbias[C];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int hi = lane >> 5, l32 = lane & 31;
+
+  bf16x8 wa[2][NS];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int n = 32 * h + l32;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int k = 16 * s + 8 * hi;
+      const int tap = k / C, c = k % C;
+      wa[h][s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(wt + ((int64_t)n * KT + tap) * C + c));
+    }
+  }
+  if (threadIdx.x < C) sbias[threadIdx.x] = (MODE == 0 && bias) ? bias[threadIdx.x] : 0.f;
+
+  auto tile_of = [&](int64_t tix, int64_t& p, int& t0) {
+    p = tix / ntiles;
+    t0 = (int)(tix - p * ntiles) * TR64;
+  };
+  // rows [r0, r0 + nrows) of a series (row r0 + r -> LDS row r) into an LDS
+  // buffer: load i covers LDS rows 8i .. 8i+7; lane L fills slot L & 7 of row
+  // 8i + (L >> 3) with chunk (L & 7) ^ ((row >> 1) & 7)
+  auto dma_rows = [&](const uint16_t* series, int r0, int nrows, unsigned char* dst) {
+    const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(series), (short)0, T * 128, 0x00020000);
+    for (int i = wave; i < nrows / 8; i += 4) {
+      const int r = 8 * i + (lane >> 3);
+      const int chunk = (lane & 7) ^ ((r >> 1) & 7);
+      const uint32_t off = (uint32_t)((r0 + r) * 128 + chunk * 16);  // rows before 0 wrap out of range
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lptr)(dst + 1024 * i), 16, off, 0, 0, 0);
+    }
+  };
+  auto fetch = [&](int64_t tix, unsigned char* dst) {
+    int64_t p;
+    int t0;
+    tile_of(tix, p, t0);
+    dma_rows(in + p * (int64_t)T * C, t0 - HALO, ROWS, dst);
+  };
+  // chunk q (of TR64 * 8 / 256) of the output tile of tile tix -> HBM
+  auto store_chunk = [&](int64_t tix, int q) {
+    int64_t p;
+    int t0;
+    tile_of(tix, p, t0);
+    const int i = (int)threadIdx.x + 256 * q;
+    const int r = i >> 3, c8 = i & 7;
+    const int t = t0 + r;
+    if (t >= T) return;
+    u32x4 v = *reinterpret_cast<const u32x4*>(otile + r * OS + 8 * c8);
+    if constexpr (MODE == 2) {
+      const u32x4 mv = *reinterpret_cast<const u32x4*>(mbuf + r * 128 + ((c8 ^ ((r >> 1) & 7)) << 4));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t mm = mv[e];
+        const uint32_t lo = (mm & 0x7fffu) != 0u && !(mm & 0x8000u) ? 0x0000ffffu : 0u;
+        const uint32_t hi2 = ((mm >> 16) & 0x7fffu) != 0u && !(mm & 0x80000000u) ? 0xffff0000u : 0u;
+        v[e] &= (lo | hi2);
+      }
+    }
+    *reinterpret_cast<u32x4*>(out + (p * (int64_t)T + t) * C + 8 * c8) = v;
+  };
+  constexpr int NSTORE = TR64 * 8 / 256;  // output chunks per thread
+  static_assert(NSTORE <= KT * C / 16, "the stores ride on the first K steps");
+  // one tile from window buffer cur while the next tile's window loads into nxt
+  int64_t prev = -1;
+  auto step = [&](int64_t tix, const unsigned char* cur, unsigned char* nxt) {
+    int64_t p;
+    int t0;
+    tile_of(tix, p, t0);
+    // this tile's window and the previous tile's stores have landed
+    __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) lgkmcnt(0)
+    __syncthreads();
+    if (tix + gridDim.x < total) fetch(tix + gridDim.x, nxt);
+
+    // MODE 0: the sums start from the bias of the accumulator's channel
+    f32x16 acc[2][2];  // [row block][channel half]
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      f32x16 a0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 b4 = MODE == 0 ? *reinterpret_cast<const f32x4*>(sbias + 32 * h + 8 * q + 4 * hi)
+                                   : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a0[4 * q + e] = b4[e];
+      }
+      acc[0][h] = a0;
+      acc[1][h] = a0;
+    }
+    // B fragments of K step s (rows 32 apart share the chunk permutation: the
+    // second block reads 4 KB further)
+    auto read_b = [&](int s, u32x4 (&v)[2]) {
+      const int k = 16 * s + 8 * hi;
+      const int tap = k / C, c8 = (k % C) >> 3;
+      const int row = 64 * wave + l32 + tap;
+      const unsigned char* src = cur + row * 128 + ((c8 ^ ((row >> 1) & 7)) << 4);
+      v[0] = *reinterpret_cast<const u32x4*>(src);
+      v[1] = *reinterpret_cast<const u32x4*>(src + 4096);
+    };
+    // fragments two K steps ahead: the reads of step s+2 are issued before the
+    // products of step s (three register sets, so no read overwrites operands
+    // still in use)
+    u32x4 vb[3][2];
+    read_b(0, vb[0]);
+    read_b(1, vb[1]);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (s + 2 < NS) read_b(s + 2, vb[(s + 2) % 3]);
+      // the previous tile's output leaves while the products run
+      if (s < NSTORE && prev >= 0) store_chunk(prev, s);
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          acc[m][h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[h][s], __builtin_bit_cast(bf16x8, vb[s % 3][m]),
+                                                             acc[m][h], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // every wave has read the previous output tile out of LDS (only LDS
+    // operations are waited for: the stores and the next window stay in flight)
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    // MODE 2: this tile's mask rows, applied when the tile is stored (next step)
+    if constexpr (MODE == 2) dma_rows(mask + p * (int64_t)T * C, t0, TR64, mbuf);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int row = 64 * wave + 32 * m + l32;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c0 = 32 * h + 8 * q + 4 * hi;  // first of the 4 channels
+          float v[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            v[e] = acc[m][h][4 * q + e];
+            if (MODE == 0) v[e] = v[e] > 0.f ? v[e] : 0.f;
+          }
+          const u32x2 pk = {(uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
+                            (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16)};
+          *reinterpret_cast<u32x2*>(otile + row * OS + c0) = pk;
+        }
+    }
+    prev = tix;
+  };
+
+  if ((int64_t)blockIdx.x < total) fetch(blockIdx.x, win0);
+  for (int64_t tix = blockIdx.x; tix < total; tix += 2 * (int64_t)gridDim.x) {
+    step(tix, win0, win1);
+    if (tix + gridDim.x < total) step(tix + gridDim.x, win1, win0);
+  }
+  if (prev >= 0) {
+    __builtin_amdgcn_s_waitcnt(0x0070);  // the last tile's mask has landed
+    __syncthreads();
+    for (int q = 0; q < NSTORE; ++q) store_chunk(prev, q);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Last layer, one real output channel: h[t] = bias + sum_{tap,c} W[tap][c]
 // in[t+tap-4][c] (64 input channels), FP32 out (P, T).  Vector arithmetic: a
 // 64-row tile's input window sits in LDS, four lanes share an output row (16
@@ -548,6 +752,14 @@ namespace {
 int st(hipError_t e) { return e == hipSuccess ? 0 : -3; }
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 constexpr int64_t kConvBlocks = 4096;
+// one resident workgroup of the 64-to-64 kernel per compute unit
+int64_t conv64_blocks() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess || n < 1)
+    n = 256;
+  return n;
+}
 bool okc(int c) { return c == 8 || c == 16 || c == 64; }
 }  // namespace
 
@@ -566,8 +778,15 @@ int whs_net_conv_fwd(const uint16_t* in, int cin, const uint16_t* w, const float
   dim3 block(cout == 64 ? 256 : 64);
 #define WHS_CONV(CI, CO, MO) \
   hipLaunchKernelGGL((k_conv<CI, CO, MO>), grid, block, 0, s, in, w, bias, mask, out, T, ntiles, total)
+  // the 64-to-64 layers: 128-row tiles, one persistent workgroup per CU
+  const int nt64 = (int)nblk(T, TR64);
+  const int64_t tot64 = P * nt64;
+  const int64_t nb64 = conv64_blocks();
+  const dim3 grid64((unsigned)(tot64 < nb64 ? tot64 : nb64));
   if (cin == 8 && cout == 64 && mode == 0) WHS_CONV(8, 64, 0);
-  else if (cin == 64 && cout == 64 && mode == 0) WHS_CONV(64, 64, 0);
+  else if (cin == 64 && cout == 64 && mode == 0)
+    hipLaunchKernelGGL((k_conv64<0>), grid64, dim3(256), 0, s, in, w, bias, mask, static_cast<uint16_t*>(out), T,
+                       nt64, tot64);
   else if (cin == 64 && cout == 16 && mode == 1) {
     // one real output channel: the vector kernel, 256 lanes per workgroup
     hipLaunchKernelGGL(k_conv_last, grid, dim3(256), 0, s, in, w, bias, static_cast<float*>(out), T, ntiles, total);

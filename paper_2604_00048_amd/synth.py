@@ -299,17 +299,11 @@ def cloud_contaminate(x: torch.Tensor, w: torch.Tensor, frac: float, gen):
 
 
 def holdout_split(w: torch.Tensor, frac: float, gen) -> torch.Tensor:
-    """Per series, ``round(frac * m)`` observed points chosen uniformly without
-    replacement; returns the held-out mask (uint8), a subset of ``w``."""
-    P, T = w.shape
-    r = torch.rand((P, T), generator=gen, device=w.device, dtype=torch.float64)
-    r = torch.where(w != 0, r, torch.full_like(r, 2.0))
-    m = (w != 0).sum(1)
-    k = torch.round(frac * m.to(torch.float64)).to(torch.long)
-    order = torch.argsort(r, dim=1)
-    rank = torch.empty_like(order)
-    rank.scatter_(1, order, torch.arange(T, device=w.device).expand(P, T).contiguous())
-    return ((rank < k[:, None]) & (w != 0)).to(torch.uint8)
+    """Each observed point is held out independently with probability ``frac``
+    (one uniform draw per point, no sort); returns the held-out mask (uint8), a
+    subset of ``w``."""
+    r = torch.rand(w.shape, generator=gen, device=w.device, dtype=torch.float64)
+    return ((r < frac) & (w != 0)).to(torch.uint8)
 
 
 # ---------------------------------------------------------------------------

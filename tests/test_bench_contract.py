@@ -73,3 +73,16 @@ def test_counter_ingest_scales_by_the_copy_calibration(tmp_path, monkeypatch, ca
     b = rec["whs_backward|heteroscedastic P=65536 T=3288 d=2 C=1"]
     assert b["bytes_per_launch"] == 2.0 * 4000.0 * 1024 + 700.0 * 1024
     assert s["source_hash"] == "0123456789abcdef"
+
+
+def test_holdout_split_is_a_seeded_subset_of_the_observed_points():
+    import torch
+    from paper_2604_00048_amd import synth
+    g = torch.Generator().manual_seed(3)
+    w = (torch.rand((64, 3288), generator=g) < 0.08).to(torch.uint8)
+    a = synth.holdout_split(w, 0.1, torch.Generator().manual_seed(9))
+    b = synth.holdout_split(w, 0.1, torch.Generator().manual_seed(9))
+    assert torch.equal(a, b)
+    assert ((a != 0) <= (w != 0)).all()
+    frac = a.sum().item() / w.sum().item()
+    assert abs(frac - 0.1) < 0.015, frac          # about 16,800 observed points

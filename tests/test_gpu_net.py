@@ -38,8 +38,9 @@ def rel(a, b):
 P, T = 3, 150   # three tiles of 64 rows with a ragged tail
 
 
-@pytest.mark.parametrize("cin", [8, 64])
-def test_conv_forward_relu(cin):
+@pytest.mark.parametrize("cin,P,T", [(8, P, T), (64, P, T), (64, 5, 300), (64, 2, 128)])
+def test_conv_forward_relu(cin, P, T):
+    # the 64-to-64 layers take 128-row tiles: 300 rows are three with a ragged tail
     x = N.bf16_round(rng.normal(size=(P, T, cin)) if cin == 8 else np.abs(rng.normal(size=(P, T, cin))))
     W = N.bf16_round(rng.normal(size=(64, 9, cin)) * 0.2)
     b = rng.normal(size=64).astype(np.float32).astype(np.float64)
@@ -61,8 +62,8 @@ def test_conv_last_layer_fp32():
     assert rel(h.cpu().double().numpy(), ref) < 1e-5
 
 
-@pytest.mark.parametrize("cin_g", [64, 16])
-def test_conv_input_gradient_masked(cin_g):
+@pytest.mark.parametrize("cin_g,P,T", [(64, P, T), (16, P, T), (64, 5, 300)])
+def test_conv_input_gradient_masked(cin_g, P, T):
     # gradient of a layer with 64 inputs and cin_g (padded) outputs
     gy = N.bf16_round(rng.normal(size=(P, T, cin_g)))
     W = N.bf16_round(rng.normal(size=(cin_g, 9, 64)) * 0.2)   # layer weights (out, tap, in)
