@@ -41,6 +41,20 @@ extern "C" {
 int whs_net_conv_fwd(const uint16_t* in, int cin, const uint16_t* w, const float* bias, int cout, int mode,
                      const uint16_t* mask, void* out, int64_t P, int T, void* stream);
 
+/* Inference through the whole network in one launch (Sec. II-C, the weight
+ * network applied to new series): h (P,T) FP32 = channel 0 of the last
+ * layer, from the (P,T,8) input, with the activations of the three hidden
+ * layers kept on chip (not written).  w0..w3 and b0..b3 are the forward
+ * weights and biases of the four layers as passed to whs_net_conv_fwd
+ * (w3 padded to 16 output channels, channel 0 used; b3[0] used).  Each hidden
+ * layer's output is rounded to bfloat16 after its ReLU, as by the layer
+ * calls; sums may be taken in another order, so h can differ from the layer
+ * calls' by FP32 rounding and by the bfloat16 rounding it feeds.  -1 on
+ * invalid arguments, -2 if T * 16 >= 2^31. */
+int whs_net_infer(const uint16_t* in8, const uint16_t* w0, const uint16_t* w1, const uint16_t* w2,
+                  const uint16_t* w3, const float* b0, const float* b1, const float* b2, const float* b3, float* h,
+                  int64_t P, int T, void* stream);
+
 /* Weight gradient of the layer with input `in` (P,T,cin) and output gradient
  * gy (P,T,cout): grad[o][k][c] = sum_{p,t} gy[p,t,o] in[p,t+k-4,c], then
  * grad[cout*9*cin + o] = sum_{p,t} gy[p,t,o].  Split over `parts`

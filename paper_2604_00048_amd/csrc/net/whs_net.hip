@@ -386,6 +386,299 @@ __global__ __launch_bounds__(256, 1) void k_conv64(const uint16_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Inference through the whole network in one kernel: h (P, T) FP32 from the
+// (P, T, 8) input, the activations of the three hidden layers kept in LDS.
+// A tile is TRI = 224 output days of one series; each hidden layer computes
+// 256 rows (its halo of 4 days per later layer included; rows outside the
+// series are set to zero, the next layer's padding):
+//   input rows  i <-> day t0 - 16 + i   (DMA, 16 B per row, next tile's in flight)
+//   layer 0 out i <-> day t0 - 12 + i   (buffer A)
+//   layer 1 out i <-> day t0 -  8 + i   (buffer B)
+//   layer 2 out i <-> day t0 -  4 + i   (buffer A again)
+//   h           i <-> day t0 + i
+// so output row i of every layer reads input rows i .. i + 8.  Layers 0-2 run
+// on v_mfma_f32_32x32x16_bf16 as out^T = W . window (weights the A operand in
+// registers: wavefront w holds 32 output channels, 32 (w >> 1) .. +31, of all
+// three layers, 316 registers; it computes rows 128 (w & 1) .. +127, four
+// 32-row products per K step).  The last layer is u = A2 . W3 with W3 the
+// (64 channels x 9 taps) matrix of its one real output channel, one
+// v_mfma_f32_16x16x32_bf16 per 16 rows and 32 channels, then
+// h[i] = bias + sum_tap u[i + tap][tap].  Sums start from the bias; each
+// layer's outputs are rounded to bfloat16 after the ReLU, as in the layer
+// kernels.  Hidden-layer rows are 128 B with 16-byte chunks permuted by XOR
+// with (row >> 1) & 7 (conflict-free fragment reads).
+// ---------------------------------------------------------------------------
+constexpr int TRI = 224;        // output days per tile of the fused inference kernel
+constexpr int NRI = 256;        // rows each hidden layer computes per tile
+constexpr int NINR = 512;       // input rows staged (two loads of 64 rows per wavefront; 264 are read)
+constexpr int ARS = NRI + 8;    // rows of a hidden-layer buffer (the last 8 stay zero)
+
+__global__ __launch_bounds__(256, 1) void k_net_infer(const uint16_t* __restrict__ in8,
+                                                      const uint16_t* __restrict__ w0,
+                                                      const uint16_t* __restrict__ w1,
+                                                      const uint16_t* __restrict__ w2,
+                                                      const uint16_t* __restrict__ w3,
+                                                      const float* __restrict__ b0, const float* __restrict__ b1,
+                                                      const float* __restrict__ b2, const float* __restrict__ b3,
+                                                      float* __restrict__ hout, int T, int ntiles, int64_t total) {
+  constexpr int C = 64;
+  constexpr int NS = KT * C / 16;  // K steps of the 64-channel layers
+  constexpr int NS0 = 5;           // K steps of layer 0 (9 taps x 8 channels, the tenth tap zero)
+  typedef __attribute__((ext_vector_type(16))) float f32x16;
+  typedef __attribute__((ext_vector_type(2))) uint32_t u32x2;
+  typedef __attribute__((address_space(3))) void* lptr;
+  __shared__ __attribute__((aligned(1024))) unsigned char inb0[NINR * 16];
+  __shared__ __attribute__((aligned(1024))) unsigned char inb1[NINR * 16];
+  __shared__ __attribute__((aligned(1024))) unsigned char bufA[ARS * 128];
+  __shared__ __attribute__((aligned(1024))) unsigned char bufB[ARS * 128];
+  __shared__ float sbias[3 * C];
+  // layer 0's weights (64 x 9 x 8) and the last layer's channel-0 weights (9 x 64),
+  // read from LDS when used (28 registers would not fit beside the others)
+  __shared__ __attribute__((aligned(16))) uint16_t sw0[C * KT * 8];
+  __shared__ __attribute__((aligned(16))) uint16_t sw3[KT * C];
+  float* const ubuf = reinterpret_cast<float*>(bufB);  // u[row][16], after layer 2 has read B
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int rg = wave & 1, chh = wave >> 1;
+  const int hi = lane >> 5, l32 = lane & 31;
+  const int n = 32 * chh + l32;  // output channel of this lane's A rows
+
+  // the two 64-channel layers' weights stay in registers
+  bf16x8 wz1[NS], wz2[NS];
+  for (int i = threadIdx.x; i < C * KT * 8 / 8; i += blockDim.x)
+    reinterpret_cast<u32x4*>(sw0)[i] = reinterpret_cast<const u32x4*>(w0)[i];
+  for (int i = threadIdx.x; i < KT * C / 8; i += blockDim.x)
+    reinterpret_cast<u32x4*>(sw3)[i] = reinterpret_cast<const u32x4*>(w3)[i];  // output channel 0's rows
+  auto load_w0 = [&](bf16x8 (&wz0)[NS0]) {
+#pragma unroll
+    for (int s = 0; s < NS0; ++s) {
+      const int tap = 2 * s + hi;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (tap < KT) v = *reinterpret_cast<const u32x4*>(sw0 + (n * KT + tap) * 8);
+      wz0[s] = __builtin_bit_cast(bf16x8, v);
+    }
+  };
+  auto load_w3 = [&](bf16x8 (&wz3)[2]) {
+    // 16x16x32 B operand: column (tap) lane % 16, channels 32 ks + 8 (lane / 16) .. +7
+    const int tap = lane & 15, cg = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (tap < KT) v = *reinterpret_cast<const u32x4*>(sw3 + tap * C + 32 * ks + 8 * cg);
+      wz3[ks] = __builtin_bit_cast(bf16x8, v);
+    }
+  };
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int k = 16 * s + 8 * hi;
+    const int tap = k / C, c = k % C;
+    wz1[s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(w1 + ((int64_t)n * KT + tap) * C + c));
+    wz2[s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(w2 + ((int64_t)n * KT + tap) * C + c));
+  }
+  if (threadIdx.x < C) {
+    sbias[threadIdx.x] = b0[threadIdx.x];
+    sbias[C + threadIdx.x] = b1[threadIdx.x];
+    sbias[2 * C + threadIdx.x] = b2[threadIdx.x];
+  }
+  const float bias3 = b3[0];
+  // rows NRI .. ARS-1 of both hidden-layer buffers are read (by rows no later
+  // layer uses) but never written: zero them once
+  for (int i = threadIdx.x; i < 8 * 128 / 4; i += blockDim.x) {
+    reinterpret_cast<uint32_t*>(bufA + NRI * 128)[i] = 0u;
+    reinterpret_cast<uint32_t*>(bufB + NRI * 128)[i] = 0u;
+  }
+
+  auto tile_of = [&](int64_t tix, int64_t& p, int& t0) {
+    p = tix / ntiles;
+    t0 = (int)(tix - p * ntiles) * TRI;
+  };
+  // input rows day t0-16 .. into an input buffer (zero outside the series);
+  // issued by every wavefront whether or not there is a tile (tix >= total
+  // loads zeros through an empty range), so the wait counts are the same on
+  // every path and waiting for other loads never waits for these
+  auto fetch = [&](int64_t tix, unsigned char* dst) {
+    int64_t p;
+    int t0;
+    const bool any = tix < total;
+    tile_of(any ? tix : 0, p, t0);
+    const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(in8 + p * (int64_t)T * 8), (short)0,
+                                                      any ? T * 16 : 0, 0x00020000);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int i = 2 * wave + j;
+      const uint32_t off = (uint32_t)((t0 - 16 + 64 * i + lane) * 16);  // days before 0 wrap out of range
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lptr)(dst + 1024 * i), 16, off, 0, 0, 0);
+    }
+  };
+  auto lds_barrier = [&]() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): LDS only, the loads in flight stay in flight
+    __builtin_amdgcn_s_barrier();
+  };
+  // accumulators of a layer start from its bias (lane channels 32 chh + 8 q + 4 hi + e)
+  auto init_acc = [&](int layer, f32x16 (&acc)[2]) {
+    f32x16 a0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x4 b4 = *reinterpret_cast<const f32x4*>(sbias + layer * C + 32 * chh + 8 * q + 4 * hi);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a0[4 * q + e] = b4[e];
+    }
+    acc[0] = a0;
+    acc[1] = a0;
+  };
+  // ReLU, zero rows outside the series, bfloat16, into a hidden-layer buffer;
+  // row i of the layer is day t0 - off + i; acc holds rows r0 + 32 b + l32
+  auto epilogue = [&](f32x16 (&acc)[2], int r0, unsigned char* dst, int t0, int off) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int row = r0 + 32 * b + l32;
+      const int t = t0 - off + row;
+      const bool in = t >= 0 && t < T;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float a = acc[b][4 * q + e];
+          v[e] = (in && a > 0.f) ? a : 0.f;
+        }
+        const u32x2 pk = {(uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
+                          (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16)};
+        const int c8 = 4 * chh + q;
+        *reinterpret_cast<u32x2*>(dst + row * 128 + ((c8 ^ ((row >> 1) & 7)) << 4) + 8 * hi) = pk;
+      }
+    }
+  };
+  // a 64-channel layer: src rows i + tap -> acc rows i, i = r0 + 32 b + l32 (two blocks)
+  auto layer64 = [&](const bf16x8 (&wz)[NS], const unsigned char* src, int r0, f32x16 (&acc)[2]) {
+    auto read_b = [&](int s, u32x4 (&v)[2]) {
+      const int k = 16 * s + 8 * hi;
+      const int tap = k / C, c8 = (k % C) >> 3;
+      const int row = r0 + l32 + tap;
+      // rows 32 apart share the chunk permutation
+      const unsigned char* a = src + row * 128 + ((c8 ^ ((row >> 1) & 7)) << 4);
+      v[0] = *reinterpret_cast<const u32x4*>(a);
+      v[1] = *reinterpret_cast<const u32x4*>(a + 4096);
+    };
+    // fragments three K steps ahead (four register sets)
+    u32x4 vb[4][2];
+    read_b(0, vb[0]);
+    read_b(1, vb[1]);
+    read_b(2, vb[2]);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (s + 3 < NS) read_b(s + 3, vb[(s + 3) & 3]);
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wz[s], __builtin_bit_cast(bf16x8, vb[s & 3][b]), acc[b], 0,
+                                                         0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+
+  float hprev = 0.f;
+  int64_t prev = -1;
+  // h of the previous tile; a buffer store on every path (dropped through the
+  // range where there is no row to write), like the loads above
+  auto store_h = [&]() {
+    int64_t p;
+    int t0;
+    tile_of(prev >= 0 ? prev : 0, p, t0);
+    const auto rs = __builtin_amdgcn_make_buffer_rsrc(hout + p * (int64_t)T, (short)0, prev >= 0 ? T * 4 : 0,
+                                                      0x00020000);
+    const int t = t0 + (int)threadIdx.x;
+    const uint32_t off = ((int)threadIdx.x < TRI && t < T) ? (uint32_t)t * 4u : 0x80000000u;
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, hprev), rs, off, 0, 0);
+  };
+  auto step = [&](int64_t tix, const unsigned char* cur, unsigned char* nxt) {
+    int64_t p;
+    int t0;
+    tile_of(tix, p, t0);
+    __builtin_amdgcn_s_waitcnt(0x0070);  // this tile's input and the previous tile's h stores have landed
+    __syncthreads();
+    fetch(tix + gridDim.x, nxt);
+    store_h();
+
+    f32x16 acc[2];
+    // layer 0: input rows i + tap (16 B rows, 8 channels; the tenth tap reads nothing)
+    bf16x8 wz0[NS0];
+    load_w0(wz0);
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+      const int r0 = 128 * rg + 64 * pass;
+      init_acc(0, acc);
+#pragma unroll
+      for (int s = 0; s < NS0; ++s) {
+        const int tap = 2 * s + hi;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int row = r0 + 32 * b + l32 + tap;
+          u32x4 v = *reinterpret_cast<const u32x4*>(cur + 16 * (tap < KT ? row : 0));
+          if (tap >= KT) v = u32x4{0u, 0u, 0u, 0u};
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wz0[s], __builtin_bit_cast(bf16x8, v), acc[b], 0, 0, 0);
+        }
+      }
+      epilogue(acc, r0, bufA, t0, 12);
+    }
+    lds_barrier();
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+      const int r0 = 128 * rg + 64 * pass;
+      init_acc(1, acc);
+      layer64(wz1, bufA, r0, acc);
+      epilogue(acc, r0, bufB, t0, 8);
+    }
+    lds_barrier();
+    // layer 2 reads B and writes A (layer 0's output, which every wave has read)
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+      const int r0 = 128 * rg + 64 * pass;
+      init_acc(2, acc);
+      layer64(wz2, bufB, r0, acc);
+      epilogue(acc, r0, bufA, t0, 4);
+    }
+    lds_barrier();  // every wave has written its rows of A and read B, which u overwrites
+    // last layer: u[row][tap] = sum_c A2[row][c] W3[tap][c]; wave w: rows 64 w .. +63
+    {
+      const int r16 = lane & 15, cg = lane >> 4;
+      bf16x8 wz3[2];
+      load_w3(wz3);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int row = 64 * wave + 16 * b + r16;
+        f32x4 u = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          const int c8 = 4 * ks + cg;
+          const u32x4 v = *reinterpret_cast<const u32x4*>(bufA + row * 128 + ((c8 ^ ((row >> 1) & 7)) << 4));
+          u = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, v), wz3[ks], u, 0, 0, 0);
+        }
+        // accumulator: rows 4 cg .. +3 of the block, column (tap) r16
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ubuf[(64 * wave + 16 * b + 4 * cg + j) * 16 + r16] = u[j];
+      }
+    }
+    lds_barrier();
+    if (threadIdx.x < TRI) {
+      float h = bias3;
+#pragma unroll
+      for (int tap = 0; tap < KT; ++tap) h += ubuf[((int)threadIdx.x + tap) * 16 + tap];
+      hprev = h;
+    }
+    prev = tix;
+  };
+
+  fetch(blockIdx.x, inb0);
+  for (int64_t tix = blockIdx.x; tix < total; tix += 2 * (int64_t)gridDim.x) {
+    step(tix, inb0, inb1);
+    if (tix + gridDim.x < total) step(tix + gridDim.x, inb1, inb0);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0070);  // the last (empty) input load before the kernel ends
+  store_h();
+}
+
+// ---------------------------------------------------------------------------
 // Last layer, one real output channel: h[t] = bias + sum_{tap,c} W[tap][c]
 // in[t+tap-4][c] (64 input channels), FP32 out (P, T).  Vector arithmetic: a
 // 64-row tile's input window sits in LDS, four lanes share an output row (16
@@ -795,6 +1088,20 @@ int whs_net_conv_fwd(const uint16_t* in, int cin, const uint16_t* w, const float
   else if (cin == 16 && cout == 64 && mode == 2) WHS_CONV(16, 64, 2);
   else return -2;
 #undef WHS_CONV
+  return st(hipGetLastError());
+}
+
+int whs_net_infer(const uint16_t* in8, const uint16_t* w0, const uint16_t* w1, const uint16_t* w2,
+                  const uint16_t* w3, const float* b0, const float* b1, const float* b2, const float* b3, float* h,
+                  int64_t P, int T, void* stream) {
+  if (!in8 || !w0 || !w1 || !w2 || !w3 || !b0 || !b1 || !b2 || !b3 || !h || P < 0 || T < 1) return -1;
+  if ((int64_t)T * 16 >= ((int64_t)1 << 31)) return -2;  // one series' input within a 32-bit buffer range
+  if (P == 0) return 0;
+  const int nt = (int)nblk(T, TRI);
+  const int64_t total = P * nt;
+  const int64_t nb = conv64_blocks();
+  hipLaunchKernelGGL(k_net_infer, dim3((unsigned)(total < nb ? total : nb)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), in8, w0, w1, w2, w3, b0, b1, b2, b3, h, T, nt, total);
   return st(hipGetLastError());
 }
 

@@ -83,7 +83,7 @@ class Learned:
     def weights(self, batch: Batch, keep: bool = False):
         """h and the per-difference weights of a batch."""
         x8 = net.net_input(batch.x_train, batch.w_train, batch.P, T_DAYS, S, self.mean, self.sd, self.feat)
-        h = self.model.forward(x8, batch.P, T_DAYS, keep=keep)
+        h = self.model.forward(x8, batch.P, T_DAYS) if keep else self.model.infer(x8, batch.P, T_DAYS)
         lam = net.head_fwd(h, batch.P, T_DAYS, S, D)
         return h, lam
 

@@ -31,6 +31,7 @@ _SZ = ctypes.c_size_t
 
 NET_SIGNATURES = {
     "whs_net_conv_fwd": (_I32, [_VP, _I32, _VP, _VP, _I32, _I32, _VP, _VP, _I64, _I32, _VP]),
+    "whs_net_infer": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I64, _I32, _VP]),
     "whs_net_wgrad_workspace_bytes": (_SZ, [_I32, _I32, _I32]),
     "whs_net_conv_wgrad": (_I32, [_VP, _I32, _VP, _I32, _VP, _VP, _SZ, _I32, _I64, _I32, _VP]),
     "whs_net_input": (_I32, [_VP, _VP, _I64, _I32, _I32, _F, _F, _VP, _VP, _VP]),
@@ -147,6 +148,15 @@ class ConvNet:
         conv_fwd(a, cin, self.wf[-1], self.bias[-1], cop, 1, None, h, P, T)
         if keep:
             self.acts = acts
+        return h
+
+    def infer(self, x8: torch.Tensor, P: int, T: int, h=None):
+        """h (P, T) FP32 from the (P, T, 8) bfloat16 input in one launch, the hidden
+        activations kept on chip (nothing saved for backward)."""
+        if h is None:
+            h = torch.empty((P, T), dtype=torch.float32, device=self.device)
+        _chk(lib().whs_net_infer(_p(x8), *[_p(w) for w in self.wf], *[_p(b) for b in self.bias], _p(h), P, T,
+                                 _s(x8.device)), "whs_net_infer")
         return h
 
     def backward(self, gh16: torch.Tensor, P: int, T: int):

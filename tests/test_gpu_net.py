@@ -189,3 +189,37 @@ def test_scalar_head_kernels():
         gt = net.scalar_head_bwd(th, torch.tensor(glam, device=dev), Pn).item()
         gref = N.scalar_head_backward(np.float32(theta), glam.astype(np.float64))
         assert abs(gt - gref) <= 1e-5 * abs(gref) + 1e-30, (gt, gref)
+
+
+def _model_with_biases(seed):
+    model = net.ConvNet(dev, seed=seed)
+    params = []
+    for i, (cin, co, cop) in enumerate(net.LAYERS):
+        flat = model.master[i].cpu().double().numpy()
+        W = flat[:co * 9 * cin].reshape(co, 9, cin)
+        b = flat[co * 9 * cin:] + 0.05 * rng.normal(size=co)
+        model.master[i][co * 9 * cin:] = torch.tensor(b, dtype=torch.float32)
+        params.append((W, b.astype(np.float32).astype(np.float64)))
+    model.pack()
+    return model, params
+
+
+@pytest.mark.parametrize("Pn,Tn", [(3, 500), (2, 224), (2, 225), (4, 5), (1, 3288)])
+def test_fused_inference_matches_layers_and_reference(Pn, Tn):
+    # one launch through all four layers (tiles of 224 days, hidden activations
+    # on chip) against the layer-by-layer kernels and the FP64 reference with
+    # bfloat16 rounding at the same points
+    model, params = _model_with_biases(7)
+    x8 = N.bf16_round(np.concatenate([rng.normal(size=(Pn, Tn, 6)), np.zeros((Pn, Tn, 2))], axis=2))
+    xt = to_bf(x8)
+    h_fused = model.infer(xt, Pn, Tn).cpu().double().numpy()
+    h_layers = model.forward(xt, Pn, Tn, keep=False).cpu().double().numpy()
+    h_ref, _ = N.forward(params, x8)
+    print(f"fused inference P={Pn} T={Tn}: vs layers {rel(h_fused, h_layers):.2e}, vs reference "
+          f"{rel(h_fused, h_ref):.2e} (layers vs reference {rel(h_layers, h_ref):.2e})", flush=True)
+    assert np.isfinite(h_fused).all()
+    assert rel(h_fused, h_ref) < 1e-2
+    assert rel(h_fused, h_layers) < 1e-2
+    # most days agree to FP32 rounding: only days whose bfloat16 roundings flipped differ
+    close = np.abs(h_fused - h_layers) <= 1e-5 * np.abs(h_layers).max()
+    assert close.mean() > 0.9, close.mean()
