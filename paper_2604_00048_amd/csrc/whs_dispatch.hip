@@ -28,9 +28,11 @@ size_t checkpoint_bytes(int64_t P, int S, int T, int D, int C) {
   // and the uneven-time one are all covered
   const int64_t nb = (P + S - 1) / S;
   size_t mx = 0;
-  for (int variant = 0; variant < 4; ++variant) {  // generic, fast solve (wide, narrow), fast backward
+  // generic, then the fast solve and adjoint for either storage type and weight kind
+  for (int variant = 0; variant < 9; ++variant) {
+    const bool fast = variant > 0, bwd = variant > 4, f64 = (variant - 1) & 1, perdiff = ((variant - 1) >> 1) & 1;
     for (int rem = C; rem > 0;) {
-      const int g = next_group(rem, variant > 0, D, variant == 3, variant == 2);
+      const int g = next_group(rem, fast, D, bwd, f64, perdiff);
       size_t b = 0;
       switch (D) {
         case 1: b = ck_bytes_d<1>(nb, S, T, g); break;

@@ -468,9 +468,20 @@ hipError_t launch_fast(const LaunchDesc& L, int c0, int write_info, hipStream_t 
   return hipGetLastError();
 }
 
+// The generic kernels take tile_depth steps, except that reading a given factor
+// (d+1 FP64 values per step) leaves room for only 16 steps at order 2 in FP32
+// storage.  Never shallower than the FP64 tile, which sizes the checkpoints.
+template <int D, int C, int ES, Src SRC>
+constexpr int generic_tile_depth() {
+  if (SRC == Src::Factor && D == 2 && ES == 4 && C == 1) return 16;
+  return tile_depth<D, C, false, ES>();
+}
+
 template <int D, int C, typename TS, Src SRC, Mode MODE, bool PERDIFF>
 hipError_t launch_generic(const LaunchDesc& L, int c0, int write_info, hipStream_t stream) {
-  constexpr int B = tile_depth<D, C, false, (int)sizeof(TS)>();
+  constexpr int B = generic_tile_depth<D, C, (int)sizeof(TS), SRC>();
+  static_assert(B >= tile_depth<D, C, false, 8>() || B >= tile_depth<D, C, false, 4>(),
+                "checkpoints are sized for the shallower of the two storage types' tiles");
   Args a;
   a.P = L.P;
   a.T = L.T;
@@ -508,20 +519,37 @@ size_t ck_bytes_for(int64_t nb, int S, int T) {
 }
 
 // RHS group sizes.  A call covers C bands by greedy groups, each one launch
-// that recomputes the same factor.  The largest group is the largest one whose
-// kernel compiles without register spills: 5 bands for the solve of order
-// d <= 2, 3 bands otherwise (fast path: interleave a multiple of 64, weights
-// and mask given); the generic path (any interleave, or a given factor) uses
-// 2 and 1.  The FP32 solve with one weight per series (narrow) stops at 3
-// bands instead: its 16-step tiles move fewer checkpoint bytes per day than
-// the 8-step tiles of 5 bands.
+// that recomputes the same factor.  On the fast path (interleave a multiple of
+// 64, weights and mask given) the largest group is the largest one whose kernel
+// compiles without register spills for its order, storage type and weight
+// kind:
+//   solve, order <= 2: 5 bands; 4 in FP64 with a weight per difference row at
+//     order 2; 3 in FP32 with one weight per series (its 16-step tiles move
+//     fewer checkpoint bytes per day than the 8-step tiles of 5 bands);
+//   solve, order 3 and 4: 3 bands;
+//   adjoint, order 1: 3; order 2: 3, but 2 in FP64 with one weight per series;
+//     order 3: 3 in FP32 with a weight per difference row, else 2; order 4: 3
+//     in FP32 with a weight per difference row, 2 in FP64 with one, else 1.
+// The generic path (any interleave, or a given factor) uses 2 and 1.
 inline bool fast_path(const LaunchDesc& L) { return !L.fac && L.S % 64 == 0 && L.P < ((int64_t)1 << 31); }
 
-inline int max_group(int D, bool bwd, bool narrow) { return (!bwd && D <= 2) ? (narrow ? 3 : 5) : 3; }
+constexpr int max_group(int D, bool bwd, bool f64, bool perdiff) {
+  if (!bwd) {
+    if (D >= 3) return 3;
+    if (!f64 && !perdiff) return 3;
+    return (D == 2 && f64 && perdiff) ? 4 : 5;
+  }
+  switch (D) {
+    case 1: return 3;
+    case 2: return (f64 && !perdiff) ? 2 : 3;
+    case 3: return (!f64 && perdiff) ? 3 : 2;
+    default: return perdiff ? (f64 ? 2 : 3) : 1;
+  }
+}
 
-inline int next_group(int remaining, bool fast, int D, bool bwd, bool narrow = false) {
+inline int next_group(int remaining, bool fast, int D, bool bwd, bool f64, bool perdiff) {
   if (fast) {
-    const int g = max_group(D, bwd, narrow);
+    const int g = max_group(D, bwd, f64, perdiff);
     return remaining < g ? remaining : g;
   }
   return remaining >= 2 ? 2 : 1;
@@ -567,25 +595,28 @@ template <int D, typename TS, Src SRC, Mode MODE, bool PERDIFF>
 hipError_t run_groups(const LaunchDesc& L, hipStream_t stream) {
   const bool fast = SRC == Src::Fused && fast_path(L);
   constexpr bool kBwd = MODE == Mode::Backward;
+  // groups wider than this are never chosen (and not compiled) for this variant
+  constexpr int kMaxG = max_group(D, kBwd, sizeof(TS) == 8, PERDIFF);
   int c0 = 0;
   while (c0 < L.C) {
-    const int g = next_group(L.C - c0, fast, D, kBwd, sizeof(TS) == 4 && !PERDIFF);
+    const int g = next_group(L.C - c0, fast, D, kBwd, sizeof(TS) == 8, PERDIFF);
     const int wi = c0 == 0;  // the first group writes info; later groups add to grad_lambda
-    hipError_t e;
+    hipError_t e = hipErrorInvalidValue;
     if constexpr (SRC == Src::Fused) {
       if (fast) {
         switch (g) {
           case 5:
-          case 4:
-            if constexpr (!kBwd && D <= 2) {
-              e = g == 5 ? launch_fast<D, 5, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream)
-                         : launch_fast<D, 4, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream);
-            } else {
-              e = hipErrorInvalidValue;  // never chosen for this order and mode
-            }
+            if constexpr (kMaxG >= 5) e = launch_fast<D, 5, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream);
             break;
-          case 3: e = launch_fast<D, 3, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
-          case 2: e = launch_fast<D, 2, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
+          case 4:
+            if constexpr (kMaxG >= 4) e = launch_fast<D, 4, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream);
+            break;
+          case 3:
+            if constexpr (kMaxG >= 3) e = launch_fast<D, 3, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream);
+            break;
+          case 2:
+            if constexpr (kMaxG >= 2) e = launch_fast<D, 2, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream);
+            break;
           default: e = launch_fast<D, 1, TS, SRC, MODE, PERDIFF>(L, c0, wi, stream); break;
         }
         if (e != hipSuccess) return e;

@@ -58,9 +58,19 @@ CASES = [
     (64, 37, 1, 5, 64, False),     # solve groups 3 + 2 in FP32, 5 in FP64
 ]
 
+# band groupings that depend on storage type and weight kind (the widest
+# spill-free group of each variant)
+GROUP_CASES = [
+    (64, 50, 2, 3, 64, False),     # adjoint 2 + 1 in FP64, 3 in FP32
+    (64, 80, 3, 5, 64, False),     # adjoint 2 + 2 + 1
+    (64, 80, 3, 5, 64, True),      # adjoint 3 + 2 in FP32, 2 + 2 + 1 in FP64
+    (64, 60, 4, 4, 64, False),     # adjoint one band at a time; solve 3 + 1
+    (64, 60, 4, 4, 64, True),      # adjoint 3 + 1 in FP32, 2 + 2 in FP64
+]
+
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-@pytest.mark.parametrize("P,T,d,C,S,per_diff", CASES)
+@pytest.mark.parametrize("P,T,d,C,S,per_diff", CASES + GROUP_CASES)
 def test_solve_parity(P, T, d, C, S, per_diff, dt):
     dtype = DT[dt]
     x, w, lam = random_case(P, T, d, C=C, per_diff=per_diff, seed=P * 7 + T, dtype=dtype,
@@ -72,7 +82,7 @@ def test_solve_parity(P, T, d, C, S, per_diff, dt):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-@pytest.mark.parametrize("P,T,d,C,S,per_diff", CASES[:7])
+@pytest.mark.parametrize("P,T,d,C,S,per_diff", CASES[:7] + GROUP_CASES)
 def test_backward_parity(P, T, d, C, S, per_diff, dt):
     dtype = DT[dt]
     x, w, lam = random_case(P, T, d, C=C, per_diff=per_diff, seed=P * 11 + T, dtype=dtype,
@@ -90,14 +100,16 @@ def test_backward_parity(P, T, d, C, S, per_diff, dt):
     # the oracle adjoint at the same (stored) z
     gx_ref, gl_ref, iref = R.vjp(x, w, lam, d, g, z=zc)
     np.testing.assert_array_equal(info2.cpu().numpy(), iref)
-    tol = 1e-9 if dt == "f64" else 1e-4
+    # FP64: 1e-9, or twice the Oettli-Prager bound of u = Omega^{-1} g where the
+    # series is conditioned so that the FP64 oracle itself may be farther off
+    tol = adjoint_tol(g, w, lam, d) if dt == "f64" else np.full(P, 1e-4)
     ex = np.abs(gx - gx_ref).max(axis=(1, 2)) / np.abs(gx_ref).max(axis=(1, 2))
-    assert ex.max() <= tol, ex.max()
+    assert (ex <= tol).all(), (ex.max(), ex[ex > tol], tol[ex > tol])
     if gl.ndim == 1:
         el = np.abs(gl - gl_ref) / np.maximum(np.abs(gl_ref), 1e-300)
     else:
         el = np.abs(gl - gl_ref).max(1) / np.abs(gl_ref).max(1)
-    assert el.max() <= tol * 10, el.max()
+    assert (el <= tol * 10).all(), (el.max(), el[el > tol * 10])
     assert (gx[w == 0] == 0).all()
 
 
