@@ -777,40 +777,73 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ in, 
     for (int i = threadIdx.x; i < (XROWS - CIN) * XS; i += blockDim.x) xT[CIN * XS + i] = 0;
   }
 
-  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+  // A unit of the staging is a pair of rows x 8 channels (two 16-byte loads).
+  // The next item's units are loaded into registers while this item's
+  // products run, and stored to LDS (transposed) after the barrier.
+  constexpr int NTH = NOUT == 64 ? 256 : 64;  // threads per workgroup (as launched)
+  constexpr int XU = (TK / 2) * (CIN / 8), GU = (GR / 2) * (NOUT / 8);
+  constexpr int UX = (XU + NTH - 1) / NTH, UG = (GU + NTH - 1) / NTH;  // units per thread
+  u32x4 px0[UX], px1[UX], pg0[UG], pg1[UG];
+  auto fetch_item = [&](int64_t it) {
+#pragma unroll
+    for (int k = 0; k < UX; ++k) px0[k] = px1[k] = u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int k = 0; k < UG; ++k) pg0[k] = pg1[k] = u32x4{0u, 0u, 0u, 0u};
+    if (it >= items) return;
     const int64_t p = it / chunks;
     const int t0 = (int)(it - p * chunks) * TK;
     const uint16_t* ip = in + p * (int64_t)T * CIN;
     const uint16_t* gp = gy + p * (int64_t)T * NOUT;
-    __syncthreads();
-    // input rows t0 .. t0+31: a unit is a pair of rows x 8 channels (two 16-byte
-    // loads); it stores 8 dwords, each the (t, t+1) pair of one channel
-    for (int i = threadIdx.x; i < (TK / 2) * (CIN / 8); i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < UX; ++k) {
+      const int i = (int)threadIdx.x + NTH * k;
+      if (i >= XU) break;
       const int up = i % (TK / 2), c0 = 8 * (i / (TK / 2));
       const int t = t0 + 2 * up;
-      u32x4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
-      if (t < T) v0 = *reinterpret_cast<const u32x4*>(ip + (int64_t)t * CIN + c0);
-      if (t + 1 < T) v1 = *reinterpret_cast<const u32x4*>(ip + (int64_t)(t + 1) * CIN + c0);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        *reinterpret_cast<uint32_t*>(xT + (c0 + 2 * q) * XS + 2 * up) = (v0[q] & 0xffffu) | (v1[q] << 16);
-        *reinterpret_cast<uint32_t*>(xT + (c0 + 2 * q + 1) * XS + 2 * up) = (v0[q] >> 16) | (v1[q] & 0xffff0000u);
-      }
+      if (t < T) px0[k] = *reinterpret_cast<const u32x4*>(ip + (int64_t)t * CIN + c0);
+      if (t + 1 < T) px1[k] = *reinterpret_cast<const u32x4*>(ip + (int64_t)(t + 1) * CIN + c0);
     }
-    // gradient rows t0-4 .. t0+35, the same way
-    for (int i = threadIdx.x; i < (GR / 2) * (NOUT / 8); i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < UG; ++k) {
+      const int i = (int)threadIdx.x + NTH * k;
+      if (i >= GU) break;
       const int rp = i % (GR / 2), n0 = 8 * (i / (GR / 2));
       const int t = t0 - HALO + 2 * rp;
-      u32x4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
-      if (t >= 0 && t < T) v0 = *reinterpret_cast<const u32x4*>(gp + (int64_t)t * NOUT + n0);
-      if (t + 1 >= 0 && t + 1 < T) v1 = *reinterpret_cast<const u32x4*>(gp + (int64_t)(t + 1) * NOUT + n0);
+      if (t >= 0 && t < T) pg0[k] = *reinterpret_cast<const u32x4*>(gp + (int64_t)t * NOUT + n0);
+      if (t + 1 >= 0 && t + 1 < T) pg1[k] = *reinterpret_cast<const u32x4*>(gp + (int64_t)(t + 1) * NOUT + n0);
+    }
+  };
+  fetch_item(blockIdx.x);
+
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    __syncthreads();
+    // the item's units into LDS: each stores 8 dwords, the (t, t+1) pair of one channel
+#pragma unroll
+    for (int k = 0; k < UX; ++k) {
+      const int i = (int)threadIdx.x + NTH * k;
+      if (i >= XU) break;
+      const int up = i % (TK / 2), c0 = 8 * (i / (TK / 2));
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        *reinterpret_cast<uint32_t*>(gT + (n0 + 2 * q) * GS + 2 * rp) = (v0[q] & 0xffffu) | (v1[q] << 16);
-        *reinterpret_cast<uint32_t*>(gT + (n0 + 2 * q + 1) * GS + 2 * rp) = (v0[q] >> 16) | (v1[q] & 0xffff0000u);
+        *reinterpret_cast<uint32_t*>(xT + (c0 + 2 * q) * XS + 2 * up) = (px0[k][q] & 0xffffu) | (px1[k][q] << 16);
+        *reinterpret_cast<uint32_t*>(xT + (c0 + 2 * q + 1) * XS + 2 * up) =
+            (px0[k][q] >> 16) | (px1[k][q] & 0xffff0000u);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < UG; ++k) {
+      const int i = (int)threadIdx.x + NTH * k;
+      if (i >= GU) break;
+      const int rp = i % (GR / 2), n0 = 8 * (i / (GR / 2));
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        *reinterpret_cast<uint32_t*>(gT + (n0 + 2 * q) * GS + 2 * rp) = (pg0[k][q] & 0xffffu) | (pg1[k][q] << 16);
+        *reinterpret_cast<uint32_t*>(gT + (n0 + 2 * q + 1) * GS + 2 * rp) =
+            (pg0[k][q] >> 16) | (pg1[k][q] & 0xffff0000u);
       }
     }
     __syncthreads();
+    fetch_item(it + gridDim.x);
     // gradient window of this lane: rows 8g .. 8g+15 of channel m (taps cut 8 of them)
     uint32_t W[8];
 #pragma unroll
