@@ -32,14 +32,21 @@ extern "C" {
 #endif
 
 /* Convolution out[t][o] = sum_{k,c} W[o][k][c] in[t+k-4][c] (zero padding).
- * mode 0: + bias, ReLU, bfloat16 out (P,T,cout)           (cin 8 or 64, cout 64)
+ * mode 0: + bias, ReLU, bfloat16 out (P,T,cout)           (cin 8 or 64, cout 64);
+ *         if `bits` is not NULL, also the ReLU bits of out: bit o % 8 of byte
+ *         bits[(p*T + t)*(cout/8) + o/8] is set where the stored out[p][t][o]
+ *         is > 0 (the mode 2 predicate), (P,T,cout/8) bytes, caller-owned
  * mode 1: + bias, FP32 out of channel 0 only, (P,T)        (cin 64, cout 16)
  * mode 2: input gradient: no bias, out[t][o] kept only where mask[t][o] > 0
- *         (mask = the layer input's stored activation; ReLU derivative),
- *         bfloat16 out (P,T,cout), w = the flipped transposed weights
- *         (cin 64 or 16 = the layer's padded outputs, cout 64). */
+ *         (mask = the layer input's stored bfloat16 activation (P,T,cout);
+ *         ReLU derivative), bfloat16 out (P,T,cout), w = the flipped
+ *         transposed weights (cin 64 or 16 = the layer's padded outputs, cout 64)
+ * mode 3: as mode 2 with mask = the activation's ReLU bits written by mode 0
+ *         (same results bit for bit, 1/16 of the mask bytes).
+ * -1 for a NULL required pointer, bits with a mode other than 0, or a mask
+ * missing in mode 2 or 3; -2 for a layer shape not listed. */
 int whs_net_conv_fwd(const uint16_t* in, int cin, const uint16_t* w, const float* bias, int cout, int mode,
-                     const uint16_t* mask, void* out, int64_t P, int T, void* stream);
+                     const void* mask, void* out, uint8_t* bits, int64_t P, int T, void* stream);
 
 /* Inference through the whole network in one launch (Sec. II-C, the weight
  * network applied to new series): h (P,T) FP32 = channel 0 of the last

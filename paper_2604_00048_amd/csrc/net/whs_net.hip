@@ -29,12 +29,35 @@ constexpr int TM = 64;   // output time rows per tile
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
 
+// one bit per bfloat16 value of a 16-byte chunk (8 channels): set where the
+// value is > 0 (not zero, sign clear)
+__device__ __forceinline__ uint8_t relu_bits(u32x4 v) {
+  uint32_t b = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    b |= (uint32_t)((v[q] & 0x7fffu) != 0u && !(v[q] & 0x8000u)) << (2 * q);
+    b |= (uint32_t)(((v[q] >> 16) & 0x7fffu) != 0u && !(v[q] & 0x80000000u)) << (2 * q + 1);
+  }
+  return (uint8_t)b;
+}
+// keep the bfloat16 values of a 16-byte chunk whose bit is set, zero the rest
+__device__ __forceinline__ u32x4 apply_bits(u32x4 v, uint32_t m) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    v[q] &= ((m >> (2 * q)) & 1u ? 0x0000ffffu : 0u) | ((m >> (2 * q + 1)) & 1u ? 0xffff0000u : 0u);
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // Convolution as implicit GEMM: out[t][n] = sum_{tap,c} Wt[n][tap][c] in[t+tap-4][c]
 // MODE 0: + bias, ReLU, bfloat16 out (P,T,NOUT)
 // MODE 1: + bias, FP32 out of channel 0 only (P,T)            (last layer; the
 //         launcher runs k_conv_last instead, which computes only that channel)
 // MODE 2: no bias, out *= (mask > 0), bfloat16 out (P,T,NOUT) (input gradient)
+// MODE 3: as MODE 2 with the mask as bits (byte (p T + t) NOUT/8 + o/8, bit o%8)
+// MODE 0 with `bits` set also writes the ReLU bits of its output in that layout
+// (bit set where the stored bfloat16 value is > 0: the MODE 2 predicate), so
+// the input gradient reads 1 bit per channel instead of the activation.
 // A tile is 64 time rows of one series; wave w computes output channels
 // 16w..16w+15 for all 64 rows (4 accumulator tiles).  Each workgroup loads
 // its weights into registers once and then walks tiles blockIdx.x,
@@ -42,8 +65,9 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __builtin_bit_cast(fl
 // ---------------------------------------------------------------------------
 template <int CIN, int NOUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wt,
-                                              const float* __restrict__ bias, const uint16_t* __restrict__ mask,
-                                              void* __restrict__ out, int T, int ntiles, int64_t total) {
+                                              const float* __restrict__ bias, const void* __restrict__ maskv,
+                                              uint8_t* __restrict__ bits, void* __restrict__ out, int T, int ntiles,
+                                              int64_t total) {
   constexpr int KTOT = KT * CIN;
   constexpr int NS = (KTOT + 31) / 32;      // K steps of 32
   constexpr int ROWS = TM + 2 * HALO;       // input window rows
@@ -159,8 +183,10 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
       }
     __syncthreads();
     uint16_t* o = static_cast<uint16_t*>(out) + p * (int64_t)T * NOUT;
-    const uint16_t* mk = mask ? mask + p * (int64_t)T * NOUT : nullptr;
+    const uint16_t* mk = MODE == 2 ? static_cast<const uint16_t*>(maskv) + p * (int64_t)T * NOUT : nullptr;
     constexpr int OCH = NOUT / 8;
+    const uint8_t* mb = MODE == 3 ? static_cast<const uint8_t*>(maskv) + p * (int64_t)T * OCH : nullptr;
+    uint8_t* ob = MODE == 0 && bits ? bits + p * (int64_t)T * OCH : nullptr;
     for (int i = threadIdx.x; i < TM * OCH; i += blockDim.x) {
       const int r = i / OCH, c8 = i % OCH;
       const int t = t0 + r;
@@ -175,15 +201,18 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
           v[q] &= (lo | hi);
         }
       }
+      if (MODE == 3) v = apply_bits(v, mb[(int64_t)t * OCH + c8]);
       *reinterpret_cast<u32x4*>(o + (int64_t)t * NOUT + 8 * c8) = v;
+      if (MODE == 0 && ob) ob[(int64_t)t * OCH + c8] = relu_bits(v);
     }
   }
   }  // tiles
 }
 
 // ---------------------------------------------------------------------------
-// The 64-in, 64-out layers (MODE 0: + bias, ReLU; MODE 2: input gradient,
-// out *= (mask > 0)) as out^T = W . window on v_mfma_f32_32x32x16_bf16.  The
+// The 64-in, 64-out layers (MODE 0: + bias, ReLU; MODE 3: input gradient,
+// out kept where its ReLU bit is set) as out^T = W . window on
+// v_mfma_f32_32x32x16_bf16.  The
 // weights are the A operand, in registers (lane l: output channel l % 32 of a
 // 32-channel half, K entries 8 (l / 32) .. +7 of each 16-wide K step); the
 // input window is the B operand, read from LDS (lane l: time row l % 32, 8
@@ -200,8 +229,11 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
 // through the buffer range) while this tile is computed, and a tile's output
 // (staged in LDS) is stored during the first K steps of the next tile, so its
 // LDS reads and stores overlap the products, and the one wait per tile is for
-// memory operations issued a whole tile earlier.  MODE 2 fetches the
-// tile's mask rows the same way and applies them when the tile is stored.
+// memory operations issued a whole tile earlier.  MODE 3 loads a tile's
+// ReLU bits (8 B per row) with its window and applies them to the sums, as
+// integer masks on the packed bfloat16 values (lane-wise selects of the
+// floats made the compiler spill); MODE 0 with `bits` writes its output's
+// ReLU bits as the tile is stored.
 // LDS rows are 128 B with the 16-byte chunks of row r permuted by XOR with
 // (r >> 1) & 7, so the 16 rows read by a quarter wavefront hit distinct banks.
 // ---------------------------------------------------------------------------
@@ -209,8 +241,10 @@ constexpr int TR64 = 256;  // time rows per tile of the 64-to-64 layers
 
 template <int MODE>
 __global__ __launch_bounds__(256, 1) void k_conv64(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wt,
-                                                   const float* __restrict__ bias, const uint16_t* __restrict__ mask,
-                                                   uint16_t* __restrict__ out, int T, int ntiles, int64_t total) {
+                                                   const float* __restrict__ bias, const void* __restrict__ maskv,
+                                                   uint8_t* __restrict__ bits, uint16_t* __restrict__ out, int T,
+                                                   int ntiles, int64_t total) {
+  static_assert(MODE == 0 || MODE == 3, "forward layer or input gradient with ReLU bits");
   constexpr int C = 64;
   constexpr int ROWS = TR64 + 2 * HALO;   // input window rows (264)
   constexpr int WB = ROWS * 128;          // bytes of one window buffer
@@ -223,7 +257,9 @@ __global__ __launch_bounds__(256, 1) void k_conv64(const uint16_t* __restrict__ 
   // of one from the loads in flight into the other and waits for neither
   __shared__ __attribute__((aligned(1024))) unsigned char win0[WB];
   __shared__ __attribute__((aligned(1024))) unsigned char win1[WB];
-  __shared__ __attribute__((aligned(1024))) unsigned char mbuf[MODE == 2 ? TR64 * 128 : 16];
+  // MODE 3: the ReLU bits of a tile, 8 bytes per row, loaded with its window
+  __shared__ __attribute__((aligned(256))) unsigned char bits0[MODE == 3 ? TR64 * 8 : 4];
+  __shared__ __attribute__((aligned(256))) unsigned char bits1[MODE == 3 ? TR64 * 8 : 4];
   __shared__ __attribute__((aligned(16))) uint16_t otile[TR64 * OS];
   __shared__ float sbias[C];
 
@@ -260,11 +296,20 @@ __global__ __launch_bounds__(256, 1) void k_conv64(const uint16_t* __restrict__ 
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lptr)(dst + 1024 * i), 16, off, 0, 0, 0);
     }
   };
-  auto fetch = [&](int64_t tix, unsigned char* dst) {
+  auto fetch = [&](int64_t tix, unsigned char* dst, unsigned char* bdst) {
     int64_t p;
     int t0;
     tile_of(tix, p, t0);
     dma_rows(in + p * (int64_t)T * C, t0 - HALO, ROWS, dst);
+    if constexpr (MODE == 3) {
+      // 8 bytes per row, loaded as dwords (T * 8 is a whole number of them, so
+      // the buffer range zeroes exactly the rows past the series)
+      const auto rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<uint8_t*>(static_cast<const uint8_t*>(maskv) + p * (int64_t)T * 8), (short)0, T * 8, 0x00020000);
+      for (int i = wave; i < TR64 * 8 / 256; i += 4)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lptr)(bdst + 256 * i), 4,
+                                                 (uint32_t)(t0 * 8 + 256 * i + 4 * lane), 0, 0, 0);
+    }
   };
   // chunk q (of TR64 * 8 / 256) of the output tile of tile tix -> HBM
   auto store_chunk = [&](int64_t tix, int q) {
@@ -276,30 +321,22 @@ __global__ __launch_bounds__(256, 1) void k_conv64(const uint16_t* __restrict__ 
     const int t = t0 + r;
     if (t >= T) return;
     u32x4 v = *reinterpret_cast<const u32x4*>(otile + r * OS + 8 * c8);
-    if constexpr (MODE == 2) {
-      const u32x4 mv = *reinterpret_cast<const u32x4*>(mbuf + r * 128 + ((c8 ^ ((r >> 1) & 7)) << 4));
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint32_t mm = mv[e];
-        const uint32_t lo = (mm & 0x7fffu) != 0u && !(mm & 0x8000u) ? 0x0000ffffu : 0u;
-        const uint32_t hi2 = ((mm >> 16) & 0x7fffu) != 0u && !(mm & 0x80000000u) ? 0xffff0000u : 0u;
-        v[e] &= (lo | hi2);
-      }
-    }
     *reinterpret_cast<u32x4*>(out + (p * (int64_t)T + t) * C + 8 * c8) = v;
+    if (MODE == 0 && bits) bits[(p * (int64_t)T + t) * 8 + c8] = relu_bits(v);
   };
   constexpr int NSTORE = TR64 * 8 / 256;  // output chunks per thread
   static_assert(NSTORE <= KT * C / 16, "the stores ride on the first K steps");
   // one tile from window buffer cur while the next tile's window loads into nxt
   int64_t prev = -1;
-  auto step = [&](int64_t tix, const unsigned char* cur, unsigned char* nxt) {
+  auto step = [&](int64_t tix, const unsigned char* cur, unsigned char* nxt, const unsigned char* bcur,
+                  unsigned char* bnxt) {
     int64_t p;
     int t0;
     tile_of(tix, p, t0);
     // this tile's window and the previous tile's stores have landed
     __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) lgkmcnt(0)
     __syncthreads();
-    if (tix + gridDim.x < total) fetch(tix + gridDim.x, nxt);
+    if (tix + gridDim.x < total) fetch(tix + gridDim.x, nxt, bnxt);
 
     // MODE 0: the sums start from the bias of the accumulator's channel
     f32x16 acc[2][2];  // [row block][channel half]
@@ -349,11 +386,12 @@ __global__ __launch_bounds__(256, 1) void k_conv64(const uint16_t* __restrict__ 
     // operations are waited for: the stores and the next window stay in flight)
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
     __builtin_amdgcn_s_barrier();
-    // MODE 2: this tile's mask rows, applied when the tile is stored (next step)
-    if constexpr (MODE == 2) dma_rows(mask + p * (int64_t)T * C, t0, TR64, mbuf);
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const int row = 64 * wave + 32 * m + l32;
+      // MODE 3: this row's 64 bits (bit c: channel c kept)
+      uint64_t rb = 0;
+      if constexpr (MODE == 3) rb = *reinterpret_cast<const uint64_t*>(bcur + 8 * row);
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -365,21 +403,27 @@ __global__ __launch_bounds__(256, 1) void k_conv64(const uint16_t* __restrict__ 
             v[e] = acc[m][h][4 * q + e];
             if (MODE == 0) v[e] = v[e] > 0.f ? v[e] : 0.f;
           }
-          const u32x2 pk = {(uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
-                            (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16)};
+          u32x2 pk = {(uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
+                      (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16)};
+          if constexpr (MODE == 3) {
+            // the 4 bits of channels c0 .. c0 + 3, each widened to 16
+            const uint32_t nib = (uint32_t)(h ? (rb >> 32) : rb) >> (8 * q + 4 * hi);
+            pk[0] &= (0u - (nib & 1u)) & 0xffffu | (0u - ((nib >> 1) & 1u)) << 16;
+            pk[1] &= (0u - ((nib >> 2) & 1u)) & 0xffffu | (0u - ((nib >> 3) & 1u)) << 16;
+          }
           *reinterpret_cast<u32x2*>(otile + row * OS + c0) = pk;
         }
     }
     prev = tix;
   };
 
-  if ((int64_t)blockIdx.x < total) fetch(blockIdx.x, win0);
+  if ((int64_t)blockIdx.x < total) fetch(blockIdx.x, win0, bits0);
   for (int64_t tix = blockIdx.x; tix < total; tix += 2 * (int64_t)gridDim.x) {
-    step(tix, win0, win1);
-    if (tix + gridDim.x < total) step(tix + gridDim.x, win1, win0);
+    step(tix, win0, win1, bits0, bits1);
+    if (tix + gridDim.x < total) step(tix + gridDim.x, win1, win0, bits1, bits0);
   }
   if (prev >= 0) {
-    __builtin_amdgcn_s_waitcnt(0x0070);  // the last tile's mask has landed
+    __builtin_amdgcn_s_waitcnt(0x0070);  // every wave has written the last output tile
     __syncthreads();
     for (int q = 0; q < NSTORE; ++q) store_chunk(prev, q);
   }
@@ -1092,9 +1136,9 @@ bool okc(int c) { return c == 8 || c == 16 || c == 64; }
 extern "C" {
 
 int whs_net_conv_fwd(const uint16_t* in, int cin, const uint16_t* w, const float* bias, int cout, int mode,
-                     const uint16_t* mask, void* out, int64_t P, int T, void* stream) {
+                     const void* mask, void* out, uint8_t* bits, int64_t P, int T, void* stream) {
   if (!in || !w || !out || P < 0 || T < 1 || !okc(cin) || (cout != 16 && cout != 64)) return -1;
-  if (mode < 0 || mode > 2 || (mode == 2 && !mask)) return -1;
+  if (mode < 0 || mode > 3 || (mode >= 2 && !mask) || (bits && mode != 0)) return -1;
   if (P == 0) return 0;
   const int ntiles = (int)nblk(T, TM);
   const int64_t total = P * ntiles;
@@ -1103,22 +1147,26 @@ int whs_net_conv_fwd(const uint16_t* in, int cin, const uint16_t* w, const float
   dim3 grid((unsigned)(total < kConvBlocks ? total : kConvBlocks));
   dim3 block(cout == 64 ? 256 : 64);
 #define WHS_CONV(CI, CO, MO) \
-  hipLaunchKernelGGL((k_conv<CI, CO, MO>), grid, block, 0, s, in, w, bias, mask, out, T, ntiles, total)
-  // the 64-to-64 layers: 128-row tiles, one persistent workgroup per CU
+  hipLaunchKernelGGL((k_conv<CI, CO, MO>), grid, block, 0, s, in, w, bias, mask, bits, out, T, ntiles, total)
+  // the 64-to-64 layers: 256-row tiles, one persistent workgroup per CU
   const int nt64 = (int)nblk(T, TR64);
   const int64_t tot64 = P * nt64;
   const int64_t nb64 = conv64_blocks();
   const dim3 grid64((unsigned)(tot64 < nb64 ? tot64 : nb64));
   if (cin == 8 && cout == 64 && mode == 0) WHS_CONV(8, 64, 0);
   else if (cin == 64 && cout == 64 && mode == 0)
-    hipLaunchKernelGGL((k_conv64<0>), grid64, dim3(256), 0, s, in, w, bias, mask, static_cast<uint16_t*>(out), T,
-                       nt64, tot64);
+    hipLaunchKernelGGL((k_conv64<0>), grid64, dim3(256), 0, s, in, w, bias, nullptr, bits,
+                       static_cast<uint16_t*>(out), T, nt64, tot64);
   else if (cin == 64 && cout == 16 && mode == 1) {
     // one real output channel: the vector kernel, 256 lanes per workgroup
     hipLaunchKernelGGL(k_conv_last, grid, dim3(256), 0, s, in, w, bias, static_cast<float*>(out), T, ntiles, total);
   }
   else if (cin == 64 && cout == 64 && mode == 2) WHS_CONV(64, 64, 2);
   else if (cin == 16 && cout == 64 && mode == 2) WHS_CONV(16, 64, 2);
+  else if (cin == 64 && cout == 64 && mode == 3)
+    hipLaunchKernelGGL((k_conv64<3>), grid64, dim3(256), 0, s, in, w, bias, mask, nullptr,
+                       static_cast<uint16_t*>(out), T, nt64, tot64);
+  else if (cin == 16 && cout == 64 && mode == 3) WHS_CONV(16, 64, 3);
   else return -2;
 #undef WHS_CONV
   return st(hipGetLastError());

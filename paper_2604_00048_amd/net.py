@@ -30,7 +30,7 @@ _F = ctypes.c_float
 _SZ = ctypes.c_size_t
 
 NET_SIGNATURES = {
-    "whs_net_conv_fwd": (_I32, [_VP, _I32, _VP, _VP, _I32, _I32, _VP, _VP, _I64, _I32, _VP]),
+    "whs_net_conv_fwd": (_I32, [_VP, _I32, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _I64, _I32, _VP]),
     "whs_net_infer": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I64, _I32, _VP]),
     "whs_net_wgrad_workspace_bytes": (_SZ, [_I32, _I32, _I32]),
     "whs_net_conv_wgrad": (_I32, [_VP, _I32, _VP, _I32, _VP, _VP, _SZ, _I32, _I64, _I32, _VP]),
@@ -90,8 +90,8 @@ def time_features(T: int, start_year: int = 2016) -> torch.Tensor:
     return torch.stack([torch.sin(a), torch.cos(a), torch.sin(2 * a), torch.cos(2 * a)], 1).float()
 
 
-def conv_fwd(inp, cin, w, bias, cout, mode, mask, out, P, T):
-    _chk(lib().whs_net_conv_fwd(_p(inp), cin, _p(w), _p(bias), cout, mode, _p(mask), _p(out), P, T,
+def conv_fwd(inp, cin, w, bias, cout, mode, mask, out, P, T, bits=None):
+    _chk(lib().whs_net_conv_fwd(_p(inp), cin, _p(w), _p(bias), cout, mode, _p(mask), _p(out), _p(bits), P, T,
                                 _s(inp.device)), "whs_net_conv_fwd")
     return out
 
@@ -135,19 +135,22 @@ class ConvNet:
             self.bias[i][:co].copy_(self.master[i][co * K * cin:])
 
     def forward(self, x8: torch.Tensor, P: int, T: int, keep: bool = True):
-        """h (P, T) FP32 from the (P, T, 8) bfloat16 input; keeps activations for backward."""
-        acts = [x8]
+        """h (P, T) FP32 from the (P, T, 8) bfloat16 input; keeps activations for backward
+        and, for the input gradients, the ReLU bits of each hidden layer's output."""
+        acts, bits = [x8], [None]
         a = x8
         for i, (cin, co, cop) in enumerate(LAYERS[:-1]):
             out = torch.empty((P, T, cop), dtype=torch.int16, device=self.device)
-            conv_fwd(a, cin, self.wf[i], self.bias[i], cop, 0, None, out, P, T)
+            b = torch.empty((P, T, cop // 8), dtype=torch.uint8, device=self.device) if keep else None
+            conv_fwd(a, cin, self.wf[i], self.bias[i], cop, 0, None, out, P, T, bits=b)
             acts.append(out)
+            bits.append(b)
             a = out
         h = torch.empty((P, T), dtype=torch.float32, device=self.device)
         cin, co, cop = LAYERS[-1]
         conv_fwd(a, cin, self.wf[-1], self.bias[-1], cop, 1, None, h, P, T)
         if keep:
-            self.acts = acts
+            self.acts, self.bits = acts, bits
         return h
 
     def infer(self, x8: torch.Tensor, P: int, T: int, h=None):
@@ -167,7 +170,7 @@ class ConvNet:
             _, self._ws = conv_wgrad(self.acts[i], cin, g, cop, self.grad[i], P, T, ws=self._ws)
             if i > 0:
                 gx = torch.empty((P, T, cin), dtype=torch.int16, device=self.device)
-                conv_fwd(g, cop, self.wd[i], None, cin, 2, self.acts[i], gx, P, T)
+                conv_fwd(g, cop, self.wd[i], None, cin, 3, self.bits[i], gx, P, T)
                 g = gx
 
     def adam(self, lr: float, b1=0.9, b2=0.999, eps=1e-8):

@@ -266,12 +266,15 @@ def test_network_entry_points_validate_arguments():
     from paper_2604_00048_amd import net
     L = net.lib()
     # unsupported channel pairs and modes, null pointers, negative sizes
-    assert L.whs_net_conv_fwd(FAKE, 32, FAKE, FAKE, 64, 0, None, FAKE, 4, 100, None) == -1
-    assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 2, None, FAKE, 4, 100, None) == -1   # mode 2 needs a mask
-    assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 3, None, FAKE, 4, 100, None) == -1
-    assert L.whs_net_conv_fwd(FAKE, 8, FAKE, FAKE, 16, 1, None, FAKE, 4, 100, None) == -2    # no such layer
-    assert L.whs_net_conv_fwd(None, 64, FAKE, FAKE, 64, 0, None, FAKE, 4, 100, None) == -1
-    assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 0, None, FAKE, 0, 100, None) == 0      # empty batch
+    assert L.whs_net_conv_fwd(FAKE, 32, FAKE, FAKE, 64, 0, None, FAKE, None, 4, 100, None) == -1
+    assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 2, None, FAKE, None, 4, 100, None) == -1  # mode 2 needs a mask
+    assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 3, None, FAKE, None, 4, 100, None) == -1  # so does mode 3
+    assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 4, FAKE, FAKE, None, 4, 100, None) == -1  # no mode 4
+    assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 2, FAKE, FAKE, FAKE, 4, 100, None) == -1  # bits: mode 0 only
+    assert L.whs_net_conv_fwd(FAKE, 8, FAKE, FAKE, 16, 1, None, FAKE, None, 4, 100, None) == -2   # no such layer
+    assert L.whs_net_conv_fwd(FAKE, 8, FAKE, FAKE, 64, 3, FAKE, FAKE, None, 4, 100, None) == -2   # nor this one
+    assert L.whs_net_conv_fwd(None, 64, FAKE, FAKE, 64, 0, None, FAKE, None, 4, 100, None) == -1
+    assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 0, None, FAKE, FAKE, 0, 100, None) == 0    # empty batch
     n = L.whs_net_wgrad_workspace_bytes(64, 64, 7)
     assert n == 7 * (64 * 9 * 64 + 64) * 4
     assert L.whs_net_conv_wgrad(FAKE, 64, FAKE, 64, FAKE, FAKE, n - 1, 7, 4, 100, None) == -4

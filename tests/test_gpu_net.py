@@ -35,19 +35,33 @@ def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
 
 
+def relu_bits(a: np.ndarray) -> np.ndarray:
+    """(P, T, C) values -> (P, T, C/8) bytes, bit c % 8 of byte c / 8 set where a > 0."""
+    return np.packbits(a > 0, axis=-1, bitorder="little")
+
+
 P, T = 3, 150   # three tiles of 64 rows with a ragged tail
 
 
 @pytest.mark.parametrize("cin,P,T", [(8, P, T), (64, P, T), (64, 5, 300), (64, 2, 128)])
 def test_conv_forward_relu(cin, P, T):
-    # the 64-to-64 layers take 128-row tiles: 300 rows are three with a ragged tail
+    # the 64-to-64 layers take 256-row tiles: 300 rows are two with a ragged tail
     x = N.bf16_round(rng.normal(size=(P, T, cin)) if cin == 8 else np.abs(rng.normal(size=(P, T, cin))))
     W = N.bf16_round(rng.normal(size=(64, 9, cin)) * 0.2)
     b = rng.normal(size=64).astype(np.float32).astype(np.float64)
     out = torch.empty((P, T, 64), dtype=torch.int16, device=dev)
-    net.conv_fwd(to_bf(x), cin, to_bf(W), torch.tensor(b, dtype=torch.float32, device=dev), 64, 0, None, out, P, T)
+    bits = torch.full((P, T, 8), 0xA5, dtype=torch.uint8, device=dev)
+    bias = torch.tensor(b, dtype=torch.float32, device=dev)
+    net.conv_fwd(to_bf(x), cin, to_bf(W), bias, 64, 0, None, out, P, T, bits=bits)
     ref = N.bf16_round(np.maximum(N.conv1d_same(x, W, b), 0.0))
-    assert ulp_diff(from_bf(out), ref) <= 1
+    got = from_bf(out)
+    assert ulp_diff(got, ref) <= 1
+    # the ReLU bits describe the stored output exactly
+    np.testing.assert_array_equal(bits.cpu().numpy(), relu_bits(got))
+    # and writing them changes nothing else
+    out2 = torch.empty_like(out)
+    net.conv_fwd(to_bf(x), cin, to_bf(W), bias, 64, 0, None, out2, P, T)
+    assert torch.equal(out, out2)
 
 
 def test_conv_last_layer_fp32():
@@ -62,7 +76,7 @@ def test_conv_last_layer_fp32():
     assert rel(h.cpu().double().numpy(), ref) < 1e-5
 
 
-@pytest.mark.parametrize("cin_g,P,T", [(64, P, T), (16, P, T), (64, 5, 300)])
+@pytest.mark.parametrize("cin_g,P,T", [(64, P, T), (16, P, T), (64, 5, 300), (64, 2, 1100), (16, 2, 1100)])
 def test_conv_input_gradient_masked(cin_g, P, T):
     # gradient of a layer with 64 inputs and cin_g (padded) outputs
     gy = N.bf16_round(rng.normal(size=(P, T, cin_g)))
@@ -73,6 +87,17 @@ def test_conv_input_gradient_masked(cin_g, P, T):
     net.conv_fwd(to_bf(gy), cin_g, to_bf(Wd), None, 64, 2, to_bf(act), out, P, T)
     ref = N.bf16_round(N.conv1d_dgrad(gy, W) * (act > 0))
     assert ulp_diff(from_bf(out), ref) <= 1
+    # the mask as ReLU bits (mode 3): zero exactly where the activation is not
+    # positive; the 64-channel gradient runs on another kernel (32x32x16
+    # products, 256-row tiles), the 16-channel one on the same kernel as mode 2
+    bits = torch.tensor(relu_bits(act)).to(dev)
+    out3 = torch.empty_like(out)
+    net.conv_fwd(to_bf(gy), cin_g, to_bf(Wd), None, 64, 3, bits, out3, P, T)
+    got3 = from_bf(out3)
+    assert ulp_diff(got3, ref) <= 1
+    assert np.all(got3[act <= 0] == 0)
+    if cin_g == 16:
+        assert torch.equal(out3, out)
 
 
 @pytest.mark.parametrize("cin,cout", [(8, 64), (64, 64), (64, 16)])
