@@ -107,7 +107,10 @@ size_t whs_workspace_bytes(const whs_desc* desc);
  * copy the results back: about two more passes over the data, for every order
  * and band count, and the uneven-date calls then accept interleave 1 too.
  * With less (but at least whs_workspace_bytes), interleave-1 calls run the
- * kernels that read the contiguous layout in place. */
+ * kernels that read the contiguous layout in place: for one band and d <= 2
+ * the partition kernel (256 lanes per series), which is the faster choice for
+ * small batches (below about 10,000 series of 3288 steps, where one lane per
+ * series leaves most of the GPU idle). */
 size_t whs_interleave_workspace_bytes(const whs_desc* desc);
 
 /* Bytes of the factor array whs_factor writes: P_pad * (d+1) * T * 8. */

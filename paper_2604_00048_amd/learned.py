@@ -22,9 +22,20 @@ import torch
 from . import net, synth, whs
 
 D = 2
-S = 64
+S = 64                # interleave of the evaluation chunks (one lane per series fills the chip)
+SMALL_BATCH = 8192    # training batches up to this size are series-contiguous
 T_DAYS = 3288
 GRID = [10.0 ** (-1.0 + 0.3 * i) for i in range(21)]
+
+
+def layout_for(P: int) -> int:
+    """Interleave of a batch of P series.  Up to a few thousand series, one lane
+    per series leaves most of the chip idle and the smoother calls wait on the
+    sequential recurrence (about 0.64 ms for the solve of 4096 or of 16384 series
+    of 3288 days); series-contiguous tensors (interleave 1) take the partition
+    kernel instead, 256 lanes per series (0.26 ms for 4096), and the network's
+    input and head kernels read them coalesced."""
+    return 1 if P <= SMALL_BATCH else S
 
 
 @dataclass
@@ -36,11 +47,13 @@ class Batch:
     hold: torch.Tensor      # interleaved held-out mask
     n_hold: int
     x_clean: torch.Tensor | None = None   # interleaved noise-free signal (cloud experiments)
+    S: int = S              # interleave of every series-side tensor of the batch
 
 
 def make_batch(P: int, seed: int, chunk: int, device, T: int = T_DAYS, frac: float = 0.1,
-               clouds: float = 0.0) -> Batch:
-    """One batch of the nine-year daily generator (band 0), with a held-out split.
+               clouds: float = 0.0, S: int | None = None) -> Batch:
+    """One batch of the nine-year daily generator (band 0), with a held-out split,
+    interleave ``S`` (``layout_for(P)`` when None).
 
     ``clouds > 0``: that fraction of the acquisitions is cloud-contaminated and
     still marked observed (the cloud mask is withheld, Sec. IV-C); the held-out
@@ -54,6 +67,8 @@ def make_batch(P: int, seed: int, chunk: int, device, T: int = T_DAYS, frac: flo
         x_obs = synth._finish(x_obs, b.w)
     hold = synth.holdout_split(b.w, frac, gen)
     w_tr = (b.w != 0) & (hold == 0)
+    if S is None:
+        S = layout_for(P)
     x_tr = torch.where(w_tr[:, :, None], x_obs, torch.zeros((), dtype=b.x.dtype, device=b.x.device))
     return Batch(P=P,
                  x_train=synth.pack_series(x_tr.float(), S),
@@ -61,7 +76,8 @@ def make_batch(P: int, seed: int, chunk: int, device, T: int = T_DAYS, frac: flo
                  x_true=synth.pack_series(x_obs.float(), S),
                  hold=synth.pack_rows(hold, S),
                  n_hold=int(hold.sum().item()),
-                 x_clean=synth.pack_series(b.clean.float(), S) if clouds > 0 else None)
+                 x_clean=synth.pack_series(b.clean.float(), S) if clouds > 0 else None,
+                 S=S)
 
 
 def input_stats(batch: Batch):
@@ -82,19 +98,20 @@ class Learned:
 
     def weights(self, batch: Batch, keep: bool = False):
         """h and the per-difference weights of a batch."""
-        x8 = net.net_input(batch.x_train, batch.w_train, batch.P, T_DAYS, S, self.mean, self.sd, self.feat)
+        x8 = net.net_input(batch.x_train, batch.w_train, batch.P, T_DAYS, batch.S, self.mean, self.sd, self.feat)
         h = self.model.forward(x8, batch.P, T_DAYS) if keep else self.model.infer(x8, batch.P, T_DAYS)
-        lam = net.head_fwd(h, batch.P, T_DAYS, S, D)
+        lam = net.head_fwd(h, batch.P, T_DAYS, batch.S, D)
         return h, lam
 
     def train_step(self, batch: Batch, lr: float) -> float:
         h, lam = self.weights(batch, keep=True)
-        z, info = whs.whs_solve(batch.x_train, batch.w_train, lam, D, batch.P)
+        # series-contiguous batches: the in-place partition kernel (staged=False)
+        z, info = whs.whs_solve(batch.x_train, batch.w_train, lam, D, batch.P, staged=False)
         loss = torch.zeros(1, dtype=torch.float64, device=self.device)
         # MSE in standardised units: (z - x)^2 / sd^2 averaged over held-out points
         g = net.mse(z, batch.x_true, batch.hold, 1.0 / (max(batch.n_hold, 1) * self.sd ** 2), loss=loss)
-        _, glam, _ = whs.whs_backward(batch.w_train, lam, z, g, D, batch.P, need_x=False)
-        gh16 = net.head_bwd(h, glam, batch.P, T_DAYS, S, D)
+        _, glam, _ = whs.whs_backward(batch.w_train, lam, z, g, D, batch.P, need_x=False, staged=False)
+        gh16 = net.head_bwd(h, glam, batch.P, T_DAYS, batch.S, D)
         self.model.backward(gh16, batch.P, T_DAYS)
         self.model.adam(lr)
         return loss.item() / max(batch.n_hold, 1) / self.sd ** 2
@@ -116,10 +133,10 @@ class LearnedScalar:
 
     def train_step(self, batch: Batch, lr: float, sd: float) -> float:
         lam = self.weights(batch)
-        z, _ = whs.whs_solve(batch.x_train, batch.w_train, lam, D, batch.P)
+        z, _ = whs.whs_solve(batch.x_train, batch.w_train, lam, D, batch.P, staged=False)
         loss = torch.zeros(1, dtype=torch.float64, device=self.device)
         g = net.mse(z, batch.x_true, batch.hold, 1.0 / (max(batch.n_hold, 1) * sd ** 2), loss=loss)
-        _, glam, _ = whs.whs_backward(batch.w_train, lam, z, g, D, batch.P, need_x=False)
+        _, glam, _ = whs.whs_backward(batch.w_train, lam, z, g, D, batch.P, need_x=False, staged=False)
         gt = net.scalar_head_bwd(self.theta, glam, batch.P)
         self.step += 1
         net._chk(net.lib().whs_net_adam(net._p(self.theta), net._p(gt), net._p(self.m), net._p(self.v), 1, lr, 0.9,
@@ -178,7 +195,7 @@ def evaluate(L: Learned, device, n_series: int = 262144, chunk: int = 65536, see
     lam_dev = []
     for i, p0 in enumerate(range(0, n_series, chunk)):
         P = min(chunk, n_series - p0)
-        b = make_batch(P, seed, i, device, clouds=clouds)
+        b = make_batch(P, seed, i, device, clouds=clouds, S=S)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, lam = L.weights(b)
