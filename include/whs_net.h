@@ -44,7 +44,7 @@ extern "C" {
  * mode 3: as mode 2 with mask = the activation's ReLU bits written by mode 0
  *         (same results bit for bit, 1/16 of the mask bytes).
  * -1 for a NULL required pointer, bits with a mode other than 0, or a mask
- * missing in mode 2 or 3; -2 for a layer shape not listed. */
+ * missing in mode 2 or 3; -2 for a layer shape not listed or T * 128 >= 2^31. */
 int whs_net_conv_fwd(const uint16_t* in, int cin, const uint16_t* w, const float* bias, int cout, int mode,
                      const void* mask, void* out, uint8_t* bits, int64_t P, int T, void* stream);
 

@@ -1139,6 +1139,8 @@ int whs_net_conv_fwd(const uint16_t* in, int cin, const uint16_t* w, const float
                      const void* mask, void* out, uint8_t* bits, int64_t P, int T, void* stream) {
   if (!in || !w || !out || P < 0 || T < 1 || !okc(cin) || (cout != 16 && cout != 64)) return -1;
   if (mode < 0 || mode > 3 || (mode >= 2 && !mask) || (bits && mode != 0)) return -1;
+  // one series' 64-channel rows within a 32-bit buffer range (pipelined kernels)
+  if ((int64_t)T * 128 >= ((int64_t)1 << 31)) return -2;
   if (P == 0) return 0;
   const int ntiles = (int)nblk(T, TM);
   const int64_t total = P * ntiles;

@@ -275,6 +275,7 @@ def test_network_entry_points_validate_arguments():
     assert L.whs_net_conv_fwd(FAKE, 8, FAKE, FAKE, 64, 3, FAKE, FAKE, None, 4, 100, None) == -2   # nor this one
     assert L.whs_net_conv_fwd(None, 64, FAKE, FAKE, 64, 0, None, FAKE, None, 4, 100, None) == -1
     assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 0, None, FAKE, FAKE, 0, 100, None) == 0    # empty batch
+    assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 0, None, FAKE, None, 4, 1 << 24, None) == -2  # 32-bit range
     n = L.whs_net_wgrad_workspace_bytes(64, 64, 7)
     assert n == 7 * (64 * 9 * 64 + 64) * 4
     assert L.whs_net_conv_wgrad(FAKE, 64, FAKE, 64, FAKE, FAKE, n - 1, 7, 4, 100, None) == -4
