@@ -29,14 +29,15 @@ constexpr int TM = 64;   // output time rows per tile
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
 
-// one bit per bfloat16 value of a 16-byte chunk (8 channels): set where the
-// value is > 0 (not zero, sign clear)
+// one bit per bfloat16 value of a 16-byte chunk (8 channels) of a ReLU output:
+// set where the value is > 0, which for these values (never negative) is where
+// its bits are not zero
 __device__ __forceinline__ uint8_t relu_bits(u32x4 v) {
   uint32_t b = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    b |= (uint32_t)((v[q] & 0x7fffu) != 0u && !(v[q] & 0x8000u)) << (2 * q);
-    b |= (uint32_t)(((v[q] >> 16) & 0x7fffu) != 0u && !(v[q] & 0x80000000u)) << (2 * q + 1);
+    b |= min(v[q] & 0xffffu, 1u) << (2 * q);
+    b |= min(v[q] >> 16, 1u) << (2 * q + 1);
   }
   return (uint8_t)b;
 }
