@@ -42,7 +42,10 @@ extern "C" {
  *         ReLU derivative), bfloat16 out (P,T,cout), w = the flipped
  *         transposed weights (cin 64 or 16 = the layer's padded outputs, cout 64)
  * mode 3: as mode 2 with mask = the activation's ReLU bits written by mode 0
- *         (same results bit for bit, 1/16 of the mask bytes).
+ *         (1/16 of the mask bytes; exactly zero where a bit is clear; for
+ *         cin 64 the products run on the pipelined kernel of the 64-to-64
+ *         forward layer, whose FP32 sums may round differently from mode 2's
+ *         by one bfloat16 step, for cin 16 the results equal mode 2's).
  * -1 for a NULL required pointer, bits with a mode other than 0, or a mask
  * missing in mode 2 or 3; -2 for a layer shape not listed or T * 128 >= 2^31. */
 int whs_net_conv_fwd(const uint16_t* in, int cin, const uint16_t* w, const float* bias, int cout, int mode,
