@@ -86,3 +86,19 @@ def test_holdout_split_is_a_seeded_subset_of_the_observed_points():
     assert ((a != 0) <= (w != 0)).all()
     frac = a.sum().item() / w.sum().item()
     assert abs(frac - 0.1) < 0.015, frac          # about 16,800 observed points
+
+
+def test_learned_batches_take_the_layout_of_their_size():
+    # training batches (a few thousand series) are series-contiguous, evaluation
+    # chunks interleaved; the same seed gives the same series in either layout
+    import torch
+    from paper_2604_00048_amd import learned, synth
+    assert learned.layout_for(4096) == 1 and learned.layout_for(learned.SMALL_BATCH) == 1
+    assert learned.layout_for(learned.SMALL_BATCH + 1) == 64 and learned.layout_for(65536) == 64
+    a = learned.make_batch(70, 5, 0, "cpu", T=120)
+    b = learned.make_batch(70, 5, 0, "cpu", T=120, S=64)
+    assert a.S == 1 and b.S == 64 and tuple(a.x_train.shape) == (70, 120, 1, 1)
+    assert torch.equal(synth.unpack_series(a.x_train, 70), synth.unpack_series(b.x_train, 70))
+    assert torch.equal(synth.unpack_rows(a.w_train, 70), synth.unpack_rows(b.w_train, 70))
+    assert torch.equal(synth.unpack_rows(a.hold, 70), synth.unpack_rows(b.hold, 70))
+    assert a.n_hold == b.n_hold > 0
