@@ -89,6 +89,30 @@ int whs_net_head_fwd(const float* h, int64_t P, int T, int S, int d, float lo, f
 int whs_net_head_bwd(const float* h, const float* glam, int64_t P, int T, int S, int d, float lo, float hi,
                      uint16_t* gh16, void* stream);
 
+/* The same dL/dh as one channel: gh (P,T) bfloat16 (the value channel 0 of
+ * whs_net_head_bwd holds), for whs_net_last_bwd. */
+int whs_net_head_bwd1(const float* h, const float* glam, int64_t P, int T, int S, int d, float lo, float hi,
+                      uint16_t* gh, void* stream);
+
+/* Backward of the last layer on its one real output channel h (Sec. II-C:
+ * the weight network's output; channels 1..15 of the padded layer carry zero
+ * gradient), from gh (P,T) bfloat16 = dL/dh (whs_net_head_bwd1), the layer's
+ * input x (P,T,64) bfloat16, its forward weights w (16,9,64) bfloat16 (channel
+ * 0 used) and the ReLU bits of x (whs_net_conv_fwd's `bits`, (P,T,8)):
+ *   dx[t][c] = sum_tap w[0][tap][c] gh[t+4-tap], kept where the bit of (t, c)
+ *              is set, bfloat16 (P,T,64);
+ *   grad[tap*64 + c] = sum_{p,t} gh[p,t] x[p,t+tap-4][c],
+ *   grad[16*9*64] = sum_{p,t} gh[p,t], every other entry of the padded
+ *   (16,9,64)+16 gradient zero.
+ * FP32 sums; the weight gradient over `parts` workgroups whose partial sums
+ * (workspace) are added in a fixed order.  The same rounding points as
+ * whs_net_conv_wgrad and whs_net_conv_fwd mode 3 on the 16-channel gradient,
+ * whose results these match to FP32 summation order.  -1 on invalid
+ * arguments, -4 for a too small workspace. */
+size_t whs_net_last_bwd_workspace_bytes(int parts);
+int whs_net_last_bwd(const uint16_t* x, const uint16_t* gh, const uint16_t* w, const uint8_t* bits, uint16_t* dx,
+                     float* grad, float* ws, size_t ws_bytes, int parts, int64_t P, int T, void* stream);
+
 /* Homoscedastic model (Sec. IV-B): one learned scalar theta (device FP32[1])
  * gives the same weight to every series, log10 lambda = lo + (hi - lo)
  * sigmoid(theta).  fwd writes lambda (FP32[P], the scalar-weight layout of

@@ -964,6 +964,170 @@ __global__ __launch_bounds__(1024) void k_wgrad_reduce(const float* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Backward of the last layer on its one real output channel (h = channel 0;
+// the padded channels 1..15 carry zero gradient), vector arithmetic:
+//   dx[t][c] = mask(t, c) * sum_tap W[0][tap][c] gh[t + 4 - tap]   (bf16 out)
+//   grad[tap][c] = sum_t gh[t] x[t + tap - 4][c],  grad_bias = sum_t gh[t]
+// with gh the stored bfloat16 dL/dh, FP32 sums, the mask the input's ReLU bits:
+// the rounding points of the 16-channel calls, without their 15 zero channels.
+// ---------------------------------------------------------------------------
+constexpr int LASTW = KT * 64;        // weights of output channel 0
+constexpr int LASTP = LASTW + 1;      // one partial: the weights' gradient, then the bias's
+constexpr int LASTR = 256;            // days per tile
+
+// gh of days t0 - 4 .. t0 + LASTR + 3 of series p into LDS (zero outside 0..T-1)
+__device__ __forceinline__ void last_stage_gh(const uint16_t* __restrict__ gh, int64_t p, int T, int t0, float* sg) {
+  for (int i = threadIdx.x; i < LASTR + 2 * HALO; i += blockDim.x) {
+    const int s = t0 - HALO + i;
+    sg[i] = (s >= 0 && s < T) ? bf2f(gh[p * (int64_t)T + s]) : 0.f;
+  }
+}
+
+// workgroups walk tiles of 256 days of one series (blockIdx.x, + gridDim.x,
+// ...) with the weights of their 8 channels in registers; thread (r, c8) takes
+// days t0 + r + 32 k and channels 8 c8 .. +7: 16 bytes of dx per day
+__global__ __launch_bounds__(256) void k_last_dgrad(const uint16_t* __restrict__ gh, const uint16_t* __restrict__ w,
+                                                    const uint8_t* __restrict__ bits, uint16_t* __restrict__ dx,
+                                                    int T, int ntiles, int64_t total) {
+  __shared__ float sw[LASTW];
+  __shared__ float sg[LASTR + 2 * HALO];
+  for (int i = threadIdx.x; i < LASTW; i += blockDim.x) sw[i] = bf2f(w[i]);
+  __syncthreads();
+  const int c8 = threadIdx.x & 7, r = threadIdx.x >> 3;
+  float wr[KT][8];
+#pragma unroll
+  for (int tap = 0; tap < KT; ++tap)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) wr[tap][e] = sw[tap * 64 + 8 * c8 + e];
+  for (int64_t tix = blockIdx.x; tix < total; tix += gridDim.x) {
+  const int64_t p = tix / ntiles;
+  const int t0 = (int)(tix - p * ntiles) * LASTR;
+  __syncthreads();  // the previous tile's gh is no longer read
+  last_stage_gh(gh, p, T, t0, sg);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < LASTR / 32; ++k) {
+    const int i = r + 32 * k;  // day t0 + i
+    const bool in = t0 + i < T;
+    float acc[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[e] = 0.f;
+    // dx day t takes gh day t + 4 - tap, LDS entry i + 8 - tap
+#pragma unroll
+    for (int tap = 0; tap < KT; ++tap) {
+      const float g = sg[i + 2 * HALO - tap];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[e] = __builtin_fmaf(wr[tap][e], g, acc[e]);
+    }
+    u32x4 v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = (uint32_t)f2bf(acc[2 * q]) | ((uint32_t)f2bf(acc[2 * q + 1]) << 16);
+    const int64_t row = p * (int64_t)T + (in ? t0 + i : T - 1);
+    v = apply_bits(v, bits[row * 8 + c8]);
+    if (in) *reinterpret_cast<u32x4*>(dx + row * 64 + 8 * c8) = v;
+  }
+  }  // tiles
+}
+
+// workgroup b walks tiles b, b + parts, ...; thread (r, c8) adds days t0 + r +
+// 32 k, channels 8 c8 .. +7; the sums are added over the wavefront by lane
+// swaps and over the four wavefronts in LDS, in a fixed order
+__global__ __launch_bounds__(256) void k_last_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ gh,
+                                                    float* __restrict__ part, int T, int ntiles, int64_t total) {
+  __shared__ float red[4][LASTP];
+  __shared__ float sg[LASTR + 2 * HALO];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c8 = threadIdx.x & 7, r = threadIdx.x >> 3;
+  float acc[KT][8];
+#pragma unroll
+  for (int tap = 0; tap < KT; ++tap)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[tap][e] = 0.f;
+  float gb = 0.f;
+  for (int64_t tix = blockIdx.x; tix < total; tix += gridDim.x) {
+    const int64_t p = tix / ntiles;
+    const int t0 = (int)(tix - p * ntiles) * LASTR;
+    __syncthreads();  // the previous tile's gh is no longer read
+    last_stage_gh(gh, p, T, t0, sg);
+    __syncthreads();
+    // all eight days' rows loaded first (days past the series read the last
+    // day and count as zero)
+    u32x4 xv[LASTR / 32];
+#pragma unroll
+    for (int k = 0; k < LASTR / 32; ++k) {
+      const int t = t0 + r + 32 * k;
+      xv[k] = *reinterpret_cast<const u32x4*>(x + (p * (int64_t)T + (t < T ? t : T - 1)) * 64 + 8 * c8);
+    }
+#pragma unroll
+    for (int k = 0; k < LASTR / 32; ++k) {
+      const int i = r + 32 * k;  // x day t0 + i
+      const bool in = t0 + i < T;
+      float xf[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        xf[2 * q] = in ? bf2f((uint16_t)(xv[k][q] & 0xffffu)) : 0.f;
+        xf[2 * q + 1] = in ? bf2f((uint16_t)(xv[k][q] >> 16)) : 0.f;
+      }
+      // x day t enters grad[tap] with gh day t + 4 - tap, LDS entry i + 8 - tap
+#pragma unroll
+      for (int tap = 0; tap < KT; ++tap) {
+        const float g = sg[i + 2 * HALO - tap];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[tap][e] = __builtin_fmaf(g, xf[e], acc[tap][e]);
+      }
+      if (c8 == 0 && in) gb += sg[i + HALO];
+    }
+  }
+  // over the eight days of the wavefront (lanes 8 apart share c8)
+#pragma unroll
+  for (int off = 8; off < 64; off <<= 1) {
+#pragma unroll
+    for (int tap = 0; tap < KT; ++tap)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[tap][e] += __shfl_xor(acc[tap][e], off);
+    gb += __shfl_xor(gb, off);
+  }
+  if (lane < 8) {
+#pragma unroll
+    for (int tap = 0; tap < KT; ++tap)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) red[wave][tap * 64 + 8 * c8 + e] = acc[tap][e];
+    if (lane == 0) red[wave][LASTW] = gb;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < LASTP; j += blockDim.x)
+    part[(int64_t)blockIdx.x * LASTP + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+}
+
+// grad (16, 9, 64) + 16 of the padded layer: channel 0's rows and bias from the
+// partials, 64 of them per workgroup, 16 lanes per output each adding every
+// 16th partial, then the 16 sums in a fixed order (as k_wgrad_reduce); the
+// workgroups past those zero every other entry
+constexpr int LASTRB = (LASTP + 63) / 64;  // reducing workgroups
+
+__global__ __launch_bounds__(1024) void k_last_reduce(const float* __restrict__ part, int nparts,
+                                                      float* __restrict__ grad) {
+  constexpr int NW = 16 * LASTW;  // padded weights, then 16 biases
+  if ((int)blockIdx.x >= LASTRB) {
+    const int j = ((int)blockIdx.x - LASTRB) * 1024 + (int)threadIdx.x;
+    if (j < NW + 16 && j >= LASTW && j != NW) grad[j] = 0.f;
+    return;
+  }
+  __shared__ float red[16][64];
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63), sl = threadIdx.x >> 6;
+  float s = 0.f;
+  if (col < LASTP)
+    for (int w = sl; w < nparts; w += 16) s += part[(int64_t)w * LASTP + col];
+  red[sl][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (sl == 0 && col < LASTP) {
+    float t = 0.f;
+    for (int k = 0; k < 16; ++k) t += red[k][threadIdx.x];
+    grad[col < LASTW ? col : NW] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // elementwise kernels
 // ---------------------------------------------------------------------------
 
@@ -1008,8 +1172,9 @@ __global__ void k_head_fwd(const float* __restrict__ h, int64_t P, int T, int S,
 
 // dL/dh from dL/dlambda (interleaved) into channel 0 of a (P, T, 16) bfloat16
 // gradient (channels 1..15 zero), the padded output of the last layer.
+template <int CH>
 __global__ void k_head_bwd(const float* __restrict__ h, const float* __restrict__ glam, int64_t P, int T, int S,
-                           int d, float lo, float hi, uint16_t* __restrict__ gh16) {
+                           int d, float lo, float hi, uint16_t* __restrict__ gh) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P * T) return;
   const int64_t p = i / T;
@@ -1024,11 +1189,15 @@ __global__ void k_head_bwd(const float* __restrict__ h, const float* __restrict_
     const float lamv = exp10f(lo + (hi - lo) * sg);
     g = glam[(b * (T - d) + k) * S + s] * lamv * 2.302585093f * (hi - lo) * sg * (1.f - sg);
   }
-  u32x4 z = {0u, 0u, 0u, 0u};
-  u32x4 v = z;
-  v[0] = (uint32_t)f2bf(g);
-  *reinterpret_cast<u32x4*>(gh16 + i * 16) = v;
-  *reinterpret_cast<u32x4*>(gh16 + i * 16 + 8) = z;
+  if constexpr (CH == 1) {
+    gh[i] = f2bf(g);
+  } else {
+    u32x4 z = {0u, 0u, 0u, 0u};
+    u32x4 v = z;
+    v[0] = (uint32_t)f2bf(g);
+    *reinterpret_cast<u32x4*>(gh + i * 16) = v;
+    *reinterpret_cast<u32x4*>(gh + i * 16 + 8) = z;
+  }
 }
 
 // g = 2 (z - x) / n at held-out points (0 elsewhere), and sum of squares into *loss.
@@ -1231,8 +1400,33 @@ int whs_net_head_bwd(const float* h, const float* glam, int64_t P, int T, int S,
                      uint16_t* gh16, void* stream) {
   if (!h || !glam || !gh16 || P < 0 || T <= d || d < 1 || S < 1) return -1;
   if (P == 0) return 0;
-  hipLaunchKernelGGL(k_head_bwd, dim3(nblk(P * T, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), h, glam, P,
-                     T, S, d, lo, hi, gh16);
+  hipLaunchKernelGGL(k_head_bwd<16>, dim3(nblk(P * T, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), h, glam,
+                     P, T, S, d, lo, hi, gh16);
+  return st(hipGetLastError());
+}
+
+int whs_net_head_bwd1(const float* h, const float* glam, int64_t P, int T, int S, int d, float lo, float hi,
+                      uint16_t* gh, void* stream) {
+  if (!h || !glam || !gh || P < 0 || T <= d || d < 1 || S < 1) return -1;
+  if (P == 0) return 0;
+  hipLaunchKernelGGL(k_head_bwd<1>, dim3(nblk(P * T, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), h, glam,
+                     P, T, S, d, lo, hi, gh);
+  return st(hipGetLastError());
+}
+
+size_t whs_net_last_bwd_workspace_bytes(int parts) { return parts > 0 ? (size_t)parts * LASTP * sizeof(float) : 0; }
+
+int whs_net_last_bwd(const uint16_t* x, const uint16_t* gh, const uint16_t* w, const uint8_t* bits, uint16_t* dx,
+                     float* grad, float* ws, size_t ws_bytes, int parts, int64_t P, int T, void* stream) {
+  if (!x || !gh || !w || !bits || !dx || !grad || !ws || P < 1 || T < 1 || parts < 1) return -1;
+  if (ws_bytes < whs_net_last_bwd_workspace_bytes(parts)) return -4;
+  const int nt = (int)nblk(T, LASTR);
+  const int64_t total = P * nt;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_last_wgrad, dim3((unsigned)parts), dim3(256), 0, s, x, gh, ws, T, nt, total);
+  hipLaunchKernelGGL(k_last_reduce, dim3(LASTRB + nblk(16 * LASTW + 16, 1024)), dim3(1024), 0, s, ws, parts, grad);
+  hipLaunchKernelGGL(k_last_dgrad, dim3((unsigned)(total < kConvBlocks ? total : kConvBlocks)), dim3(256), 0, s, gh, w,
+                     bits, dx, T, nt, total);
   return st(hipGetLastError());
 }
 

@@ -111,8 +111,8 @@ class Learned:
         # MSE in standardised units: (z - x)^2 / sd^2 averaged over held-out points
         g = net.mse(z, batch.x_true, batch.hold, 1.0 / (max(batch.n_hold, 1) * self.sd ** 2), loss=loss)
         _, glam, _ = whs.whs_backward(batch.w_train, lam, z, g, D, batch.P, need_x=False, staged=False)
-        gh16 = net.head_bwd(h, glam, batch.P, T_DAYS, batch.S, D)
-        self.model.backward(gh16, batch.P, T_DAYS)
+        gh = net.head_bwd1(h, glam, batch.P, T_DAYS, batch.S, D)
+        self.model.backward1(gh, batch.P, T_DAYS)
         self.model.adam(lr)
         return loss.item() / max(batch.n_hold, 1) / self.sd ** 2
 

@@ -37,6 +37,9 @@ NET_SIGNATURES = {
     "whs_net_input": (_I32, [_VP, _VP, _I64, _I32, _I32, _F, _F, _VP, _VP, _VP]),
     "whs_net_head_fwd": (_I32, [_VP, _I64, _I32, _I32, _I32, _F, _F, _VP, _VP]),
     "whs_net_head_bwd": (_I32, [_VP, _VP, _I64, _I32, _I32, _I32, _F, _F, _VP, _VP]),
+    "whs_net_head_bwd1": (_I32, [_VP, _VP, _I64, _I32, _I32, _I32, _F, _F, _VP, _VP]),
+    "whs_net_last_bwd_workspace_bytes": (_SZ, [_I32]),
+    "whs_net_last_bwd": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _I32, _I64, _I32, _VP]),
     "whs_net_mse": (_I32, [_VP, _VP, _VP, _I64, _F, _VP, _VP, _VP]),
     "whs_net_adam": (_I32, [_VP, _VP, _VP, _VP, _I64, _F, _F, _F, _F, _I32, _VP]),
     "whs_net_pack_weights": (_I32, [_VP, _I32, _I32, _I32, _VP, _VP, _VP]),
@@ -173,6 +176,27 @@ class ConvNet:
                 conv_fwd(g, cop, self.wd[i], None, cin, 3, self.bits[i], gx, P, T)
                 g = gx
 
+    def backward1(self, gh: torch.Tensor, P: int, T: int, parts: int = 1024):
+        """Parameter gradients from dL/dh as one channel, (P, T) bfloat16
+        (``head_bwd1``): the last layer's backward on that channel only
+        (``whs_net_last_bwd``), then the hidden layers as in ``backward``."""
+        i = len(LAYERS) - 1
+        cin, co, cop = LAYERS[i]
+        n = int(lib().whs_net_last_bwd_workspace_bytes(parts))
+        if self._ws is None or self._ws.numel() * 4 < n:
+            self._ws = torch.empty(n // 4 + 1, dtype=torch.float32, device=self.device)
+        g = torch.empty((P, T, cin), dtype=torch.int16, device=self.device)
+        _chk(lib().whs_net_last_bwd(_p(self.acts[i]), _p(gh), _p(self.wf[i]), _p(self.bits[i]), _p(g),
+                                    _p(self.grad[i]), _p(self._ws), self._ws.numel() * 4, parts, P, T,
+                                    _s(self.device)), "whs_net_last_bwd")
+        for i in range(len(LAYERS) - 2, -1, -1):
+            cin, co, cop = LAYERS[i]
+            _, self._ws = conv_wgrad(self.acts[i], cin, g, cop, self.grad[i], P, T, ws=self._ws)
+            if i > 0:
+                gx = torch.empty((P, T, cin), dtype=torch.int16, device=self.device)
+                conv_fwd(g, cop, self.wd[i], None, cin, 3, self.bits[i], gx, P, T)
+                g = gx
+
     def adam(self, lr: float, b1=0.9, b2=0.999, eps=1e-8):
         self.step += 1
         for i, (cin, co, cop) in enumerate(LAYERS):
@@ -209,6 +233,14 @@ def head_bwd(h, glam, P, T, S, d, out=None, lo=LO, hi=HI):
     if out is None:
         out = torch.empty((P, T, 16), dtype=torch.int16, device=h.device)
     _chk(lib().whs_net_head_bwd(_p(h), _p(glam), P, T, S, d, lo, hi, _p(out), _s(h.device)), "whs_net_head_bwd")
+    return out
+
+
+def head_bwd1(h, glam, P, T, S, d, out=None, lo=LO, hi=HI):
+    """dL/dh as one channel, (P, T) bfloat16 bits (int16)."""
+    if out is None:
+        out = torch.empty((P, T), dtype=torch.int16, device=h.device)
+    _chk(lib().whs_net_head_bwd1(_p(h), _p(glam), P, T, S, d, lo, hi, _p(out), _s(h.device)), "whs_net_head_bwd1")
     return out
 
 

@@ -276,6 +276,13 @@ def test_network_entry_points_validate_arguments():
     assert L.whs_net_conv_fwd(None, 64, FAKE, FAKE, 64, 0, None, FAKE, None, 4, 100, None) == -1
     assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 0, None, FAKE, FAKE, 0, 100, None) == 0    # empty batch
     assert L.whs_net_conv_fwd(FAKE, 64, FAKE, FAKE, 64, 0, None, FAKE, None, 4, 1 << 24, None) == -2  # 32-bit range
+    # the last layer's one-channel backward
+    n = L.whs_net_last_bwd_workspace_bytes(8)
+    assert n == 8 * (9 * 64 + 1) * 4 and L.whs_net_last_bwd_workspace_bytes(0) == 0
+    assert L.whs_net_last_bwd(FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, n, 8, 4, 100, None) == -1   # no bits
+    assert L.whs_net_last_bwd(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, n, 8, 0, 100, None) == -1   # P < 1
+    assert L.whs_net_last_bwd(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, n - 4, 8, 4, 100, None) == -4
+    assert L.whs_net_head_bwd1(None, FAKE, 4, 100, 64, 2, 0.0, 1.0, FAKE, None) == -1
     n = L.whs_net_wgrad_workspace_bytes(64, 64, 7)
     assert n == 7 * (64 * 9 * 64 + 64) * 4
     assert L.whs_net_conv_wgrad(FAKE, 64, FAKE, 64, FAKE, FAKE, n - 1, 7, 4, 100, None) == -4

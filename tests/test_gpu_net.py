@@ -195,12 +195,64 @@ def test_whole_network_forward_backward():
     gh16[:, :, 0] = gh
     model.backward(to_bf(gh16), Pn, Tn)
     grads = N.backward(params, acts, gh)
+    padded = [model.grad[i].clone() for i in range(len(net.LAYERS))]
     for i, (cin, co, cop) in enumerate(net.LAYERS):
         g = model.grad[i].cpu().double().numpy()
         gw = g[:cop * 9 * cin].reshape(cop, 9, cin)[:co]
         gb = g[cop * 9 * cin:cop * 9 * cin + co]
         assert rel(gw, grads[i][0]) < 2e-2, i
         assert rel(gb, grads[i][1]) < 2e-2, i
+    # the same from dL/dh as one channel: the last layer's backward on that channel
+    model.backward1(to_bf(gh), Pn, Tn)
+    for i in range(len(net.LAYERS)):
+        assert rel(model.grad[i].cpu().double().numpy(), padded[i].cpu().double().numpy()) < 1e-3, i
+
+
+@pytest.mark.parametrize("P,T", [(3, 150), (2, 1100), (1, 5)])
+def test_last_layer_backward_on_its_one_channel(P, T):
+    # the last layer's input (64 channels), its weights (channel 0 real, 15 zero
+    # rows of padding), dL/dh stored in bfloat16; T = 5 is shorter than the taps
+    x = N.bf16_round(np.maximum(rng.normal(size=(P, T, 64)), 0.0))
+    W = np.zeros((16, 9, 64))
+    W[0] = N.bf16_round(rng.normal(size=(9, 64)) * 0.2)
+    gh = N.bf16_round(rng.normal(size=(P, T)))
+    bits = torch.tensor(relu_bits(x)).to(dev)
+    L = net.lib()
+    parts = 7
+    ws = torch.empty(int(L.whs_net_last_bwd_workspace_bytes(parts)) // 4, dtype=torch.float32, device=dev)
+    dx = torch.empty((P, T, 64), dtype=torch.int16, device=dev)
+    grad = torch.full((16 * 9 * 64 + 16,), 7.0, dtype=torch.float32, device=dev)
+    xs, ghs, Ws = to_bf(x), to_bf(gh), to_bf(W)
+    assert L.whs_net_last_bwd(net._p(xs), net._p(ghs), net._p(Ws), net._p(bits), net._p(dx), net._p(grad),
+                              net._p(ws), ws.numel() * 4, parts, P, T, net._s(torch.device(dev))) == 0
+    # against the FP64 reference at the kernels' rounding points
+    ref_dx = N.bf16_round(N.conv1d_dgrad(gh[:, :, None], W[:1]) * (x > 0))
+    got_dx = from_bf(dx)
+    assert ulp_diff(got_dx, ref_dx) <= 1
+    assert np.all(got_dx[x <= 0] == 0)
+    gW, gb = N.conv1d_wgrad(x, gh[:, :, None])
+    g = grad.cpu().double().numpy()
+    assert rel(g[:9 * 64], gW[0].reshape(-1)) < 1e-5
+    assert abs(g[16 * 9 * 64] - gb[0]) <= 1e-5 * max(np.abs(gh).sum(), 1.0)
+    pad = np.concatenate([g[9 * 64:16 * 9 * 64], g[16 * 9 * 64 + 1:]])
+    assert np.all(pad == 0)
+    # against the 16-channel calls on the same values (dL/dh in channel 0)
+    g16 = np.zeros((P, T, 16))
+    g16[:, :, 0] = gh
+    grad16 = torch.empty_like(grad)
+    net.conv_wgrad(xs, 64, to_bf(g16), 16, grad16, P, T)
+    assert rel(g, grad16.cpu().double().numpy()) < 1e-5
+    Wd = np.transpose(W[:, ::-1, :], (2, 1, 0)).copy()
+    dx16 = torch.empty_like(dx)
+    net.conv_fwd(to_bf(g16), 16, to_bf(Wd), None, 64, 3, bits, dx16, P, T)
+    assert ulp_diff(from_bf(dx16), got_dx) <= 1
+    # the one-channel head gradient is channel 0 of the padded one
+    h = torch.tensor(rng.normal(size=(P, T)), dtype=torch.float32, device=dev)
+    d, S = 2, 64
+    glam = synth.pack_rows(torch.tensor(rng.normal(size=(P, T - d)), dtype=torch.float32), S).to(dev)
+    a16 = net.head_bwd(h, glam, P, T, S, d)
+    a1 = net.head_bwd1(h, glam, P, T, S, d)
+    assert torch.equal(a16[:, :, 0], a1)
 
 
 def test_scalar_head_kernels():
