@@ -33,11 +33,13 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X vector FP64
 GCV_FLOPS_PER_STEP = {1: 31, 2: 50, 3: 75, 4: 106}
 
 
-def alg_bytes(T: int, d: int, C: int, esz: int, per_diff: bool):
-    """Algorithmic HBM bytes per series: every API tensor once per pass at its dtype."""
+def alg_bytes(T: int, d: int, C: int, esz: int, per_diff: bool, w_bits: bool = False):
+    """Algorithmic HBM bytes per series: every API tensor once per pass at its dtype
+    (the 0/1 weights one byte per day, or one bit when packed)."""
     lam = esz * (T - d) if per_diff else esz
-    fwd = esz * T * C + T + lam + esz * T * C                        # x, w, lambda in; z out
-    bwd = esz * T * C + T + lam + esz * T * C + esz * T * C + lam    # g, w, lambda, z in; grad_x, grad_lambda out
+    wb = T / 8 if w_bits else T
+    fwd = esz * T * C + wb + lam + esz * T * C                        # x, w, lambda in; z out
+    bwd = esz * T * C + wb + lam + esz * T * C + esz * T * C + lam    # g, w, lambda, z in; grad_x, grad_lambda out
     return fwd, bwd
 
 
@@ -89,7 +91,7 @@ def _mean_counter(rows, name_part: str, counter: str):
     return sum(vals) / len(vals), len(vals)
 
 
-def ingest_counters(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, P, T, d):
+def ingest_counters(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, P, T, d, w_bits=False):
     """HBM bytes per launch of the two headline kernels from FETCH_SIZE and WRITE_SIZE
     (KiB per dispatch), each scaled by what the counter reads for a plain 256 MiB
     device copy (``--calibrate-copy``)."""
@@ -98,8 +100,8 @@ def ingest_counters(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, P, T, d)
     cw, _ = _mean_counter(_counter_rows(cal_write_dir), "copy", "WRITE_SIZE")
     fs, ws = copy_kib / cf, copy_kib / cw
     fr, wr = _counter_rows(fetch_dir), _counter_rows(write_dir)
-    workload = f"heteroscedastic P={P} T={T} d={d} C=1"
-    fb, bb = alg_bytes(T, d, 1, 4, True)
+    workload = f"heteroscedastic P={P} T={T} d={d} C=1" + (" w bits" if w_bits else "")
+    fb, bb = alg_bytes(T, d, 1, 4, True, w_bits)
     rec = {}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(path):
@@ -409,6 +411,7 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--fwd-bwd", action="store_true", help="multiband workload: time the adjoint with the solve")
     ap.add_argument("--interleave", type=int, default=64)
+    ap.add_argument("--w-bits", action="store_true", help="heteroscedastic workload: weights packed eight to a byte")
     ap.add_argument("--in-place", action="store_true",
                     help="interleave 1: read the contiguous layout in place instead of through interleaved copies")
     ap.add_argument("--n-uneven", type=int, default=100000)
@@ -442,7 +445,7 @@ def main():
 
     if args.ingest_counters:
         P = args.P or 65536
-        ingest_counters(*args.ingest_counters, P=P, T=args.T, d=args.d)
+        ingest_counters(*args.ingest_counters, P=P, T=args.T, d=args.d, w_bits=args.w_bits)
         return
 
     if args.calibrate_copy:
@@ -521,13 +524,14 @@ def bench_hetero(args):
         # series-contiguous: the workspace that runs the interleaved kernels on copies
         nws = max(nws, int(whs.lib().whs_interleave_workspace_bytes(ctypes.byref(desc))))
     ws = torch.empty(max(nws, 8), dtype=torch.uint8, device=dev)
+    w_in = synth.pack_bits(pk.w) if args.w_bits else pk.w
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
     print(f"# inputs generated in {t_gen:.1f}s; workspace {ws.numel() / 1e6:.1f} MB", file=sys.stderr, flush=True)
 
     def step():
-        whs.whs_solve(pk.x, pk.w, pk.lam, d, P, z=z, info=info, workspace=ws)
-        whs.whs_backward(pk.w, pk.lam, z, g, d, P, grad_x=gx, grad_lambda=gl, info=info, workspace=ws)
+        whs.whs_solve(pk.x, w_in, pk.lam, d, P, z=z, info=info, workspace=ws)
+        whs.whs_backward(w_in, pk.lam, z, g, d, P, grad_x=gx, grad_lambda=gl, info=info, workspace=ws)
 
     for _ in range(args.warmup):
         step()
@@ -542,9 +546,9 @@ def bench_hetero(args):
     start.record()
     for k in range(K):
         ev[k][0].record()
-        whs.whs_solve(pk.x, pk.w, pk.lam, d, P, z=z, info=info, workspace=ws)
+        whs.whs_solve(pk.x, w_in, pk.lam, d, P, z=z, info=info, workspace=ws)
         ev[k][1].record()
-        whs.whs_backward(pk.w, pk.lam, z, g, d, P, grad_x=gx, grad_lambda=gl, info=info, workspace=ws)
+        whs.whs_backward(w_in, pk.lam, z, g, d, P, grad_x=gx, grad_lambda=gl, info=info, workspace=ws)
         ev[k][2].record()
     end.record()
     torch.cuda.synchronize()
@@ -559,11 +563,11 @@ def bench_hetero(args):
 
     print(f"# timed {K} steps: {total_ms / K:.3f} ms per step", file=sys.stderr, flush=True)
     copy_gbs = copy_ceiling(dev)
-    fb, bb = alg_bytes(T, d, 1, 4, True)
+    fb, bb = alg_bytes(T, d, 1, 4, True, args.w_bits)
     bwd_gbs = bb * P / (bwd_ms * 1e-3) / 1e9
     fwd_gbs = fb * P / (fwd_ms * 1e-3) / 1e9
     step_gbs = (fb + bb) * P / (ms_step * 1e-3) / 1e9
-    workload = f"heteroscedastic P={P} T={T} d={d} C=1"
+    workload = f"heteroscedastic P={P} T={T} d={d} C=1" + (" w bits" if args.w_bits else "")
     traffic = measured_traffic("whs_backward", workload)
     out = {
         "metric": METRIC,
@@ -580,8 +584,10 @@ def bench_hetero(args):
         "data": "synthetic",
         "config": {
             "workload": f"heteroscedastic smoother fwd+bwd: P={P} series, T={T} daily steps, d={d}, C=1 band, "
-                        "per-difference lambda (log10 GP field), FP32 storage / FP64 arithmetic",
+                        "per-difference lambda (log10 GP field), FP32 storage / FP64 arithmetic"
+                        + (", 0/1 weights packed eight to a byte" if args.w_bits else ""),
             "P": P, "T": T, "d": d, "C": 1, "storage": "f32", "interleave": S,
+            **({"w_format": "bits"} if args.w_bits else {}),
             **({"contiguous_path": "in place" if args.in_place else "interleaved copies"} if S == 1 else {}),
         },
         "roofline": {

@@ -29,6 +29,9 @@
  *   one contiguous, coalesced row:
  *       x, z, g, grad_x     : element ((b*T + t)*C + c)*S + s
  *       w (uint8 0/1)       : element (b*T + t)*S + s
+ *       w as bits (w_format WHS_W_BITS, S a multiple of 64): bit s % 8 of
+ *                             byte ((b*T + t)*S + s) / 8, the same element
+ *                             index with 8 weights per byte
  *       lambda, grad_lambda : SCALAR   -> element p
  *                             PER_DIFF -> element (b*(T-d) + k)*S + s, 0 <= k < T-d
  *       factor (FP64)       : element ((b*(d+1) + i)*T + t)*S + s
@@ -63,6 +66,13 @@ typedef enum {
 
 typedef enum { WHS_F32 = 0, WHS_F64 = 1 } whs_dtype;
 typedef enum { WHS_LAMBDA_SCALAR = 0, WHS_LAMBDA_PER_DIFF = 1 } whs_lambda_kind;
+/* The 0/1 weights w of eq. (2) as one byte each, or packed eight to a byte:
+ * 1/8 of the bytes for data that carry one bit per day.  WHS_W_BITS is taken
+ * by whs_solve, whs_backward and whs_solve_noalloc on the daily grid with one
+ * band (n_rhs = 1), factor NULL, an interleave that is a multiple of 64 and
+ * P < 2^31; every other call, and those otherwise, return
+ * WHS_ERR_UNSUPPORTED.  Results are those of the same call with bytes. */
+typedef enum { WHS_W_BYTES = 0, WHS_W_BITS = 1 } whs_w_format;
 
 typedef struct {
   int64_t n_series;    /* P >= 0; P = 0 is a no-op                               */
@@ -75,6 +85,7 @@ typedef struct {
                        /* 2^31 bytes, else WHS_ERR_UNSUPPORTED (use S = 64)       */
   int32_t dtype;       /* whs_dtype: storage type of x, z, g, lambda and grads    */
   int32_t lambda_kind; /* whs_lambda_kind                                         */
+  int32_t w_format;    /* whs_w_format: 0/1 weights as bytes (0) or bits (1)      */
 } whs_desc;
 
 /* Human-readable text of a status code (static storage). */

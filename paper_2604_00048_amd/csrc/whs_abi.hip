@@ -36,6 +36,7 @@ int check_desc(const whs_desc* d) {
   if (d->n_series < 0 || d->T < 1 || d->d < 1 || d->n_rhs < 1 || d->interleave < 1) return WHS_ERR_ARG;
   if (d->dtype != WHS_F32 && d->dtype != WHS_F64) return WHS_ERR_ARG;
   if (d->lambda_kind != WHS_LAMBDA_SCALAR && d->lambda_kind != WHS_LAMBDA_PER_DIFF) return WHS_ERR_ARG;
+  if (d->w_format != WHS_W_BYTES && d->w_format != WHS_W_BITS) return WHS_ERR_ARG;
   if (d->d > kMaxD) return WHS_ERR_UNSUPPORTED;
   if (d->T <= d->d) return WHS_ERR_ARG;
   // grid of ceil(P/256) blocks must fit one launch dimension
@@ -53,7 +54,17 @@ whs::LaunchDesc make_launch(const whs_desc* d) {
   L.S = d->interleave;
   L.f64 = d->dtype == WHS_F64;
   L.perdiff = d->lambda_kind == WHS_LAMBDA_PER_DIFF;
+  L.wbits = d->w_format == WHS_W_BITS;
   return L;
+}
+
+// Weights as bits are read by the fused one-band two-sweep kernels on the
+// daily grid only: interleave a multiple of 64 (a block's row of w is then
+// whole dwords), no given factor, P < 2^31 (the same conditions select those
+// kernels), one band
+bool bits_ok(const whs_desc* d, const double* factor) {
+  if (d->w_format != WHS_W_BITS) return true;
+  return d->interleave % 64 == 0 && !factor && d->n_series < ((int64_t)1 << 31) && d->n_rhs == 1;
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? WHS_OK : WHS_ERR_HIP; }
@@ -225,6 +236,7 @@ int whs_factor(const whs_desc* desc, const uint8_t* w, const void* lambda, doubl
                void* stream) {
   int st = check_desc(desc);
   if (st != WHS_OK) return st;
+  if (desc->w_format == WHS_W_BITS) return WHS_ERR_UNSUPPORTED;
   if (desc->n_series == 0) return WHS_OK;
   if (!w || !lambda || !factor) return WHS_ERR_ARG;
   if (!aligned(lambda, elem(desc)) || !aligned(factor, 8) || !aligned(info, 4)) return WHS_ERR_ARG;
@@ -240,6 +252,7 @@ int whs_solve(const whs_desc* desc, const uint8_t* w, const void* lambda, const 
               void* z, int32_t* info, void* workspace, size_t workspace_bytes, void* stream) {
   int st = check_desc(desc);
   if (st != WHS_OK) return st;
+  if (!bits_ok(desc, factor)) return WHS_ERR_UNSUPPORTED;
   if (desc->n_series == 0) return WHS_OK;
   if (!w || !x || !z) return WHS_ERR_ARG;
   if (!factor && !lambda) return WHS_ERR_ARG;
@@ -282,6 +295,7 @@ int whs_backward(const whs_desc* desc, const uint8_t* w, const void* lambda, con
                  size_t workspace_bytes, void* stream) {
   int st = check_desc(desc);
   if (st != WHS_OK) return st;
+  if (!bits_ok(desc, factor)) return WHS_ERR_UNSUPPORTED;
   if (desc->n_series == 0) return WHS_OK;
   if (!w || !z || !g) return WHS_ERR_ARG;
   if (!factor && !lambda) return WHS_ERR_ARG;
@@ -318,6 +332,7 @@ int whs_solve_coef(const whs_desc* desc, const double* coef, const uint8_t* w, c
                    void* z, int32_t* info, void* workspace, size_t workspace_bytes, void* stream) {
   int st = check_desc(desc);
   if (st != WHS_OK) return st;
+  if (desc->w_format == WHS_W_BITS) return WHS_ERR_UNSUPPORTED;
   if (desc->n_series == 0) return desc->interleave % 64 == 0 || desc->interleave == 1 ? WHS_OK : WHS_ERR_UNSUPPORTED;
   const bool stg = use_staged(desc, nullptr, workspace_bytes);
   if (!stg && (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31))) return WHS_ERR_UNSUPPORTED;
@@ -343,6 +358,7 @@ int whs_backward_coef(const whs_desc* desc, const double* coef, const uint8_t* w
                       size_t workspace_bytes, void* stream) {
   int st = check_desc(desc);
   if (st != WHS_OK) return st;
+  if (desc->w_format == WHS_W_BITS) return WHS_ERR_UNSUPPORTED;
   if (desc->n_series == 0) return desc->interleave % 64 == 0 || desc->interleave == 1 ? WHS_OK : WHS_ERR_UNSUPPORTED;
   const bool stg = use_staged(desc, nullptr, workspace_bytes);
   if (!stg && (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31))) return WHS_ERR_UNSUPPORTED;
@@ -376,6 +392,7 @@ int whs_gcv(const whs_desc* desc, const uint8_t* w, const void* x, const double*
             void* stream) {
   int st = check_desc(desc);
   if (st != WHS_OK) return st;
+  if (desc->w_format == WHS_W_BITS) return WHS_ERR_UNSUPPORTED;
   if (desc->n_rhs != 1 || desc->lambda_kind != WHS_LAMBDA_SCALAR) return WHS_ERR_UNSUPPORTED;
   if (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31)) return WHS_ERR_UNSUPPORTED;
   if (n_grid < 1) return WHS_ERR_ARG;
@@ -411,6 +428,7 @@ int whs_variance(const whs_desc* desc, const uint8_t* w, const void* lambda, voi
                  void* workspace, size_t workspace_bytes, void* stream) {
   int st = check_desc(desc);
   if (st != WHS_OK) return st;
+  if (desc->w_format == WHS_W_BITS) return WHS_ERR_UNSUPPORTED;
   if (desc->n_rhs != 1) return WHS_ERR_ARG;
   if (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31)) return WHS_ERR_UNSUPPORTED;
   if (desc->n_series == 0) return WHS_OK;

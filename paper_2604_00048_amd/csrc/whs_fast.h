@@ -63,17 +63,23 @@ struct FastArgs {
   int glam_accum;
 };
 
-template <int D, int C, int B, typename TS, bool BWD, bool PERDIFF, bool TAB = false>
+template <int D, int C, int B, typename TS, bool BWD, bool PERDIFF, bool TAB = false, bool WB = false>
 struct Fast {
   static constexpr int NF = ck_fields<D, C>();
   static constexpr uint32_t ES = sizeof(TS);
 
   struct Tile {
     TS x[B][C];
-    uint32_t w[B];
+    uint32_t w[WB ? 1 : B];  // 0/1 weights (bytes)
+    uint32_t wm;             // the same as bits s of one register (weights as bits)
     TS lam[B];
     TS z[B][C];
   };
+  // the 0/1 weight of step s of a tile
+  static __device__ __forceinline__ bool wt(const Tile& tl, int s) {
+    if constexpr (WB) return (tl.wm >> s) & 1u;
+    else return tl.w[s] != 0u;
+  }
 
   // wave-uniform
   const TS* xb;
@@ -90,6 +96,21 @@ struct Fast {
   uint32_t lx, lw, lc;
   double lam_scalar;
   bool accum;
+  // w as bits (WB): a row of w is S / 8 bytes and lane s reads bit s & 31 (its
+  // lane index & 31) of the dword at byte lw (every lane of the dword reads the
+  // same address)
+  static constexpr bool wbits = WB;
+
+  // the 0/1 weight of this lane at row `row` of the w range rw
+  template <int POLICY>
+  __device__ __forceinline__ uint32_t load_w(const __amdgpu_buffer_rsrc_t rw, int row) const {
+    if constexpr (WB)
+      return (__builtin_amdgcn_raw_buffer_load_b32(rw, lw + (uint32_t)(row * (S >> 3)), 0, POLICY) >>
+              (__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)) & 31u)) & 1u;
+    else
+      return __builtin_amdgcn_raw_buffer_load_b8(rw, lw + (uint32_t)(row * S), 0, POLICY);
+  }
+  __device__ __forceinline__ uint32_t w_row_bytes() const { return WB ? (uint32_t)(S >> 3) : (uint32_t)S; }
 
   // row k of D's coefficient table (wave-uniform); zero outside 0..T-D-1
   __device__ __forceinline__ void crow(int k, double (&c)[D + 1]) const {
@@ -111,13 +132,18 @@ struct Fast {
     const int rows = rows_from(t0, T);
     const int tb = rows > 0 ? t0 : 0;
     const auto rx = make_rsrc(xb + (int64_t)tb * Ctot * S, rows * Rx);
-    const auto rw = make_rsrc(wb + (int64_t)tb * S, rows * S);
+    const auto rw = make_rsrc(wb + (int64_t)tb * w_row_bytes(), rows * w_row_bytes());
 #pragma unroll
     for (int s = 0; s < B; ++s) {
 #pragma unroll
       for (int c = 0; c < C; ++c)
         tl.x[s][c] = bload<TS, SWEEP2 ? kStream : kKeep>(rx, lx + (uint32_t)((s * Ctot + c0 + c) * S) * ES);
-      tl.w[s] = __builtin_amdgcn_raw_buffer_load_b8(rw, lw + (uint32_t)(s * S), 0, SWEEP2 ? kStream : kKeep);
+      if constexpr (WB) {
+        if (s == 0) tl.wm = 0u;
+        tl.wm |= load_w<SWEEP2 ? kStream : kKeep>(rw, s) << s;
+      } else {
+        tl.w[s] = load_w<SWEEP2 ? kStream : kKeep>(rw, s);
+      }
     }
     if constexpr (PERDIFF) {
       const int rl = rows_from(t0, T - D);
@@ -140,7 +166,7 @@ struct Fast {
   template <bool FULL>
   __device__ __forceinline__ void step(State<D, C>& st, const Tile& tl, int s, int t, double (&l)[D + 1],
                                        double& dt, double& invdt, double (&yt)[C]) const {
-    const bool obs = tl.w[s] != 0u;
+    const bool obs = wt(tl, s);
     double lt;
     if constexpr (PERDIFF) {
       lt = to_f64(tl.lam[s]);
@@ -252,7 +278,7 @@ struct Fast {
       const int t = t0 + s;
       double l[D + 1], dt, invdt, yt[C];
       step<FULL>(st, tl, s, t, l, dt, invdt, yt);
-      nobs += tl.w[s] != 0u;
+      nobs += wt(tl, s) ? 1 : 0;
       ok = ok & (pivot_good(dt) | (!FULL && t >= T));
     }
     return ok;
@@ -310,7 +336,7 @@ struct Fast {
         for (int c = 0; c < C; ++c)
           bstore<TS, kStream>(ro, lx + (uint32_t)((s * Ctot + c0 + c) * S) * ES, from_f64<TS>(failed ? qnan : zt[c]));
       } else {
-        const bool obs = tl.w[s] != 0u;
+        const bool obs = wt(tl, s);
         if (ob) {
 #pragma unroll
           for (int c = 0; c < C; ++c)
@@ -376,10 +402,10 @@ struct Fast {
   __device__ int first_bad_pivot(int t_end) const {
     State<D, C> st;
     st.zero();
-    const auto rw = make_rsrc(wb, (uint32_t)T * S);
+    const auto rw = make_rsrc(wb, (uint32_t)T * w_row_bytes());
     const auto rl = make_rsrc(lb ? (const void*)lb : (const void*)wb, PERDIFF ? (uint32_t)(T - D) * S * ES : 0u);
     for (int t = 0; t < t_end && t < T; ++t) {
-      const bool obs = __builtin_amdgcn_raw_buffer_load_b8(rw, lw + (uint32_t)(t * S), 0, 0) != 0;
+      const bool obs = load_w<0>(rw, t) != 0;
       const double ltv = PERDIFF ? to_f64(bload<TS>(rl, lx + (uint32_t)(t * S) * ES)) : (t < T - D ? lam_scalar : 0.0);
       double lwv[D + 1];
       lwv[0] = ltv;
@@ -416,7 +442,7 @@ struct Fast {
     nt = a.nt;
     Rx = (uint32_t)Ctot * S * ES;
     xb = static_cast<const TS*>(a.rhs) + bidx * T * Ctot * S;
-    wb = a.w + bidx * T * S;
+    wb = a.w + bidx * T * (int64_t)w_row_bytes();
     lb = PERDIFF ? static_cast<const TS*>(a.lam) + bidx * (T - D) * S : nullptr;
     zb = BWD ? static_cast<const TS*>(a.zin) + bidx * T * Ctot * S : nullptr;
     ob = a.out ? static_cast<TS*>(a.out) + bidx * T * Ctot * S : nullptr;
@@ -428,7 +454,7 @@ struct Fast {
     // makes their loads read zero and drops their stores
     constexpr uint32_t kDead = 0x80000000u;
     lx = live ? (uint32_t)s_in * ES : kDead;
-    lw = live ? (uint32_t)s_in : kDead;
+    lw = live ? (WB ? ((uint32_t)s_in >> 5) << 2 : (uint32_t)s_in) : kDead;
     lc = live ? (uint32_t)s_in * 8u : kDead;
     lam_scalar = (!PERDIFF && live) ? to_f64(static_cast<const TS*>(a.lam)[p]) : 0.0;
 
@@ -507,9 +533,9 @@ struct Fast {
   }
 };
 
-template <int D, int C, int B, typename TS, bool BWD, bool PERDIFF, bool TAB>
+template <int D, int C, int B, typename TS, bool BWD, bool PERDIFF, bool TAB, bool WB = false>
 __global__ __launch_bounds__(256) void k_fast(FastArgs a) {
-  Fast<D, C, B, TS, BWD, PERDIFF, TAB> k;
+  Fast<D, C, B, TS, BWD, PERDIFF, TAB, WB> k;
   k.run(a);
 }
 

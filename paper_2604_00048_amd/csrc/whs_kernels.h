@@ -22,6 +22,7 @@ struct LaunchDesc {
   int32_t* info;
   double* ws;         // checkpoint workspace
   const double* coef = nullptr;  // rows of D on uneven sample times, (T-D) x (D+1); null: daily grid
+  bool wbits = false;            // w one bit per series (S a multiple of 64, fused path only)
 };
 
 size_t checkpoint_bytes(int64_t P, int S, int T, int D, int C);

@@ -439,7 +439,7 @@ constexpr int fast_tile_depth() {
   return tile_depth<D, C, TAB, ES>();
 }
 
-template <int D, int C, typename TS, Src SRC, Mode MODE, bool PERDIFF, bool TAB = false>
+template <int D, int C, typename TS, Src SRC, Mode MODE, bool PERDIFF, bool TAB = false, bool WB = false>
 hipError_t launch_fast(const LaunchDesc& L, int c0, int write_info, hipStream_t stream) {
   constexpr int B = fast_tile_depth<D, C, TAB, (int)sizeof(TS), MODE == Mode::Backward, PERDIFF>();
   static_assert(B >= tile_depth<D, C, TAB, (int)sizeof(TS)>(), "checkpoints are sized for tile_depth");
@@ -463,7 +463,7 @@ hipError_t launch_fast(const LaunchDesc& L, int c0, int write_info, hipStream_t 
   f.glam_accum = c0 > 0;
   const int threads = 256;
   const int64_t blocks = (L.P + threads - 1) / threads;
-  hipLaunchKernelGGL((k_fast<D, C, B, TS, MODE == Mode::Backward, PERDIFF, TAB>), dim3((unsigned)blocks),
+  hipLaunchKernelGGL((k_fast<D, C, B, TS, MODE == Mode::Backward, PERDIFF, TAB, WB>), dim3((unsigned)blocks),
                      dim3(threads), 0, stream, f);
   return hipGetLastError();
 }
@@ -603,6 +603,9 @@ hipError_t run_groups(const LaunchDesc& L, hipStream_t stream) {
     const int wi = c0 == 0;  // the first group writes info; later groups add to grad_lambda
     hipError_t e = hipErrorInvalidValue;
     if constexpr (SRC == Src::Fused) {
+      // weights as bits: one band, one launch (the ABI admits nothing else)
+      if (fast && L.wbits) return L.C == 1 ? launch_fast<D, 1, TS, SRC, MODE, PERDIFF, false, true>(L, 0, 1, stream)
+                                           : hipErrorInvalidValue;
       if (fast) {
         switch (g) {
           case 5:

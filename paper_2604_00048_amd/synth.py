@@ -161,6 +161,24 @@ def unpack_rows(vi: torch.Tensor, P: int) -> torch.Tensor:
     return vi.permute(0, 2, 1).reshape(nb * S, n)[:P]
 
 
+def pack_bits(wi: torch.Tensor) -> torch.Tensor:
+    """Interleaved 0/1 weights ``[nb][T][S]`` (uint8) -> eight per byte,
+    ``[nb][T][S/8]``: bit ``s % 8`` of byte ``s / 8`` of each row."""
+    nb, T, S = wi.shape
+    if S % 8:
+        raise ValueError("the interleave must be a multiple of 8")
+    b = (wi != 0).to(torch.uint8).view(nb, T, S // 8, 8)
+    shifts = torch.arange(8, dtype=torch.uint8, device=wi.device)
+    return (b << shifts).sum(dim=3, dtype=torch.int32).to(torch.uint8)
+
+
+def unpack_bits(wb: torch.Tensor) -> torch.Tensor:
+    """Inverse of ``pack_bits``: ``[nb][T][S/8]`` -> ``[nb][T][S]`` (0/1 uint8)."""
+    nb, T, S8 = wb.shape
+    shifts = torch.arange(8, dtype=torch.uint8, device=wb.device)
+    return ((wb.unsqueeze(3) >> shifts) & 1).reshape(nb, T, S8 * 8)
+
+
 # ---------------------------------------------------------------------------
 # workloads
 # ---------------------------------------------------------------------------

@@ -28,6 +28,7 @@ LIB_PATH = os.path.join(_HERE, "libwhs.so")
 
 WHS_F32, WHS_F64 = 0, 1
 WHS_LAMBDA_SCALAR, WHS_LAMBDA_PER_DIFF = 0, 1
+WHS_W_BYTES, WHS_W_BITS = 0, 1
 WHS_OK, WHS_ERR_ARG, WHS_ERR_UNSUPPORTED, WHS_ERR_HIP, WHS_ERR_WORKSPACE = 0, -1, -2, -3, -4
 
 
@@ -40,6 +41,7 @@ class WhsDesc(ctypes.Structure):
         ("interleave", ctypes.c_int32),
         ("dtype", ctypes.c_int32),
         ("lambda_kind", ctypes.c_int32),
+        ("w_format", ctypes.c_int32),
     ]
 
 
@@ -155,8 +157,21 @@ def _need_gpu(*ts):
             raise ValueError("tensors must be contiguous in the interleaved layout")
 
 
-def make_desc(P: int, T: int, d: int, C: int, S: int, dtype: int, lambda_kind: int) -> WhsDesc:
-    return WhsDesc(int(P), int(T), int(d), int(C), int(S), int(dtype), int(lambda_kind))
+def make_desc(P: int, T: int, d: int, C: int, S: int, dtype: int, lambda_kind: int, w_format: int = 0) -> WhsDesc:
+    return WhsDesc(int(P), int(T), int(d), int(C), int(S), int(dtype), int(lambda_kind), int(w_format))
+
+
+def _w_format(w: torch.Tensor, nb: int, T: int, S: int) -> int:
+    """WHS_W_BYTES for uint8 weights of shape (nb, T, S), WHS_W_BITS for the
+    packed form (nb, T, S / 8) of an interleave that is a multiple of 64
+    (``synth.pack_bits``)."""
+    if w.dtype != torch.uint8:
+        raise ValueError("w must be uint8")
+    if tuple(w.shape) == (nb, T, S):
+        return WHS_W_BYTES
+    if S % 64 == 0 and tuple(w.shape) == (nb, T, S // 8):
+        return WHS_W_BITS
+    raise ValueError(f"w must be uint8 of shape {(nb, T, S)}" + (f" or {(nb, T, S // 8)} (bits)" if S % 64 == 0 else ""))
 
 
 def _lambda_kind(lam: torch.Tensor | None, P: int, nb: int, T: int, d: int, S: int) -> int:
@@ -250,12 +265,11 @@ def whs_solve(x: torch.Tensor, w: torch.Tensor, lam: torch.Tensor | None, d: int
     """
     _need_gpu(x, w, lam, factor, z, info, workspace, coef)
     nb, T, C, S, P = _geometry(x, P)
-    if tuple(w.shape) != (nb, T, S) or w.dtype != torch.uint8:
-        raise ValueError(f"w must be uint8 of shape {(nb, T, S)}")
+    wf = _w_format(w, nb, T, S)
     if lam is not None and lam.dtype != x.dtype:
         raise TypeError("lambda must have the storage dtype of x")
     kind = _lambda_kind(lam, P, nb, T, d, S)
-    desc = make_desc(P, T, d, C, S, _dtype_code(x), kind)
+    desc = make_desc(P, T, d, C, S, _dtype_code(x), kind, wf)
     if z is None:
         z = torch.empty_like(x)
     if info is None:
@@ -281,11 +295,10 @@ def whs_solve_noalloc(x: torch.Tensor, w: torch.Tensor, lam: torch.Tensor, d: in
     pass ``z`` and ``info`` to keep this call free of allocations too."""
     _need_gpu(x, w, lam, z, info)
     nb, T, C, S, P = _geometry(x, P)
-    if tuple(w.shape) != (nb, T, S) or w.dtype != torch.uint8:
-        raise ValueError(f"w must be uint8 of shape {(nb, T, S)}")
+    wf = _w_format(w, nb, T, S)
     if lam.dtype != x.dtype:
         raise TypeError("lambda must have the storage dtype of x")
-    desc = make_desc(P, T, d, C, S, _dtype_code(x), _lambda_kind(lam, P, nb, T, d, S))
+    desc = make_desc(P, T, d, C, S, _dtype_code(x), _lambda_kind(lam, P, nb, T, d, S), wf)
     if z is None:
         z = torch.empty_like(x)
     if info is None:
@@ -308,7 +321,7 @@ def whs_backward(w: torch.Tensor, lam: torch.Tensor | None, z: torch.Tensor, g: 
     if tuple(g.shape) != tuple(z.shape) or g.dtype != z.dtype:
         raise ValueError("g must match z in shape and dtype")
     kind = _lambda_kind(lam, P, nb, T, d, S) if lambda_kind is None else int(lambda_kind)
-    desc = make_desc(P, T, d, C, S, _dtype_code(z), kind)
+    desc = make_desc(P, T, d, C, S, _dtype_code(z), kind, _w_format(w, nb, T, S))
     if need_x and grad_x is None:
         grad_x = torch.empty_like(g)
     if need_lambda and grad_lambda is None:

@@ -345,3 +345,42 @@ def test_noalloc_entry_point_checks_sizes_before_touching_the_device():
     assert L.whs_solve_noalloc(ctypes.byref(empty), None, None, None, None, None, None) == whs.WHS_OK
     bad = whs.make_desc(100, 2, 2, 1, 64, whs.WHS_F32, whs.WHS_LAMBDA_PER_DIFF)  # T <= d
     assert L.whs_solve_noalloc(ctypes.byref(bad), FAKE, FAKE, FAKE, FAKE, None, None) == whs.WHS_ERR_ARG
+
+
+def test_weights_as_bits_are_taken_where_built():
+    # fused one-band solve and adjoint on the daily grid with an interleave that is
+    # a multiple of 64; everything else refuses the bit format without launching
+    L = whs.lib()
+    bad = whs.make_desc(10, 50, 2, 1, 64, 0, 0, 2)
+    assert _solve_raw(bad, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 30) == -1          # no such format
+    for P, C, S in [(10, 1, 1), (10, 2, 64), (10, 1, 32)]:
+        desc = whs.make_desc(P, 50, 2, C, S, 0, 0, whs.WHS_W_BITS)
+        assert _solve_raw(desc, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 30) == -2
+    desc = whs.make_desc(10, 50, 2, 1, 64, 0, 0, whs.WHS_W_BITS)
+    # a given factor, the factor export, GCV, the variance and uneven dates
+    assert L.whs_solve(ctypes.byref(desc), FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, 1 << 30, None) == -2
+    assert L.whs_factor(ctypes.byref(desc), FAKE, FAKE, FAKE, None, None) == -2
+    assert L.whs_gcv(ctypes.byref(desc), FAKE, FAKE, FAKE, 3, FAKE, None, None, FAKE, 0, None) == -2
+    assert L.whs_variance(ctypes.byref(desc), FAKE, FAKE, FAKE, None, FAKE, 1 << 30, None) == -2
+    assert L.whs_solve_coef(ctypes.byref(desc), FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, 1 << 30, None) == -2
+    # and the empty batch of a supported call is a no-op
+    empty = whs.make_desc(0, 50, 2, 1, 64, 0, 0, whs.WHS_W_BITS)
+    assert _solve_raw(empty, None, None, None, None, None, 0) == 0
+
+
+def test_bit_packing_round_trip():
+    import torch
+    from paper_2604_00048_amd import synth
+    g = torch.Generator().manual_seed(4)
+    w = (torch.rand((3, 17, 128), generator=g) < 0.3).to(torch.uint8)
+    b = synth.pack_bits(w)
+    assert tuple(b.shape) == (3, 17, 16) and b.dtype == torch.uint8
+    assert torch.equal(synth.unpack_bits(b), w)
+    # bit s % 8 of byte s / 8
+    s = 77
+    assert torch.equal((b[:, :, s // 8] >> (s % 8)) & 1, w[:, :, s])
+    # the binding tells the formats apart by shape
+    assert whs._w_format(w, 3, 17, 128) == whs.WHS_W_BYTES
+    assert whs._w_format(b, 3, 17, 128) == whs.WHS_W_BITS
+    with pytest.raises(ValueError):
+        whs._w_format(b[:, :, :8], 3, 17, 128)
