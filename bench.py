@@ -112,8 +112,10 @@ def ingest_counters(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, P, T, d,
     print("| API call | kernel | dispatches | algorithmic GB | HBM read GB | HBM write GB | traffic / algorithmic |")
     print("|---|---|---|---|---|---|---|")
     for call, bwd, alg in (("whs_solve", "false", fb), ("whs_backward", "true", bb)):
+        # k_fast<d, 1 band, tile, float, adjoint?, per-difference weights, uneven dates?, weights as bits?>
         part = f"k_fast<{d}, 1, "
-        names = sorted({k for k, c, v in fr if part in k and f"float, {bwd}, true, false>" in k})
+        tail = f"float, {bwd}, true, false, {'true' if w_bits else 'false'}>"
+        names = sorted({k for k, c, v in fr if part in k and tail in k})
         if len(names) != 1:
             raise SystemExit(f"expected one {call} kernel, found {names}")
         kname = names[0]

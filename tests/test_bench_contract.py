@@ -54,8 +54,8 @@ def _fake_rocprof(dirpath, rows):
 
 
 def test_counter_ingest_scales_by_the_copy_calibration(tmp_path, monkeypatch, capsys):
-    solve = "void whs::k_fast<2, 1, 24, float, false, true, false>(whs::FastArgs)"
-    back = "void whs::k_fast<2, 1, 24, float, true, true, false>(whs::FastArgs)"
+    solve = "void whs::k_fast<2, 1, 24, float, false, true, false, false>(whs::FastArgs)"
+    back = "void whs::k_fast<2, 1, 24, float, true, true, false, false>(whs::FastArgs)"
     _fake_rocprof(tmp_path / "f", [(solve, "FETCH_SIZE", 1000.0), (solve, "FETCH_SIZE", 3000.0),
                                    (back, "FETCH_SIZE", 4000.0)])
     _fake_rocprof(tmp_path / "w", [(solve, "WRITE_SIZE", 500.0), (back, "WRITE_SIZE", 700.0)])
