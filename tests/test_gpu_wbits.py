@@ -66,3 +66,14 @@ def test_bits_at_the_headline_size():
     torch.cuda.synchronize()
     assert torch.equal(i1, i2) and int((i1 != 0).sum().item()) == 0
     assert torch.equal(z1, z2) and torch.equal(gx1, gx2) and torch.equal(gl1, gl2)
+
+
+def test_bits_through_the_entry_point_that_allocates_nothing():
+    P, T, d, S = 300, 700, 2, 64
+    x, w, lam = random_case(P, T, d, per_diff=True, seed=11, dtype=torch.float32)
+    xt, wt, wb, lt = both(x, w, lam, S, torch.float32)
+    z1, i1 = whs.whs_solve(xt, wt, lt, d, P)
+    z2, i2 = whs.whs_solve_noalloc(xt, wb, lt, d, P)
+    torch.cuda.synchronize()
+    assert torch.equal(i1, i2)
+    np.testing.assert_array_equal(from_device_series(z1, P), from_device_series(z2, P))
