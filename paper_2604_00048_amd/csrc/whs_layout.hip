@@ -1,9 +1,11 @@
 // Layout changes between series-contiguous arrays (P, L) and the interleaved
 // time-major layout (ceil(P/64), L, 64) the throughput kernels read: element
 // (p, j) sits at p*L + j in one and at ((p/64)*L + j)*64 + p%64 in the other.
-// A workgroup moves one 64 x 64 tile through LDS so both sides are read and
-// written in 64-element rows.  Interleaving zero-fills the slots of the last
-// block that hold no series.
+// A workgroup moves one tile through LDS so both sides are read and written in
+// whole rows.  Interleaving zero-fills the slots of the last block that hold no
+// series.  4-byte and 1-byte elements take wide accesses where the rows allow
+// them; other cases (8-byte elements, rows whose starts are not aligned) take
+// one element per access.
 #include <hip/hip_runtime.h>
 
 #include "whs_kernels.h"
@@ -41,6 +43,165 @@ __global__ __launch_bounds__(256) void k_interleave(const E* __restrict__ src, E
   }
 }
 
+// Workgroups go out round-robin over the 8 XCDs.  The k-th workgroup of XCD x
+// takes tile x * (grid / 8) + k of a numbering with the step tile fastest, so
+// the tiles that share a series block's rows run at about the same time on one
+// XCD, whose L2 then joins the halves of the cache lines they split.  The grid
+// is a multiple of 8; a workgroup past the last tile returns at once.
+__device__ inline bool xcd_tile(int64_t n_step_tiles, int64_t n_tiles, int64_t& b, int64_t& by) {
+  const int64_t id = blockIdx.x, per = gridDim.x / 8;
+  const int64_t u = (id % 8) * per + id / 8;
+  if (u >= n_tiles) return false;
+  b = u / n_step_tiles;
+  by = u % n_step_tiles;
+  return true;
+}
+
+// 4-byte elements, a tile of 64 series x 64 steps.  The series-contiguous side
+// is read or written V elements per access (its rows start V-aligned: L % V == 0),
+// the interleaved side four (16 bytes: a quarter of a step's 64-series row).
+template <int V>
+__global__ __launch_bounds__(256) void k_interleave4(const float* __restrict__ src, float* __restrict__ dst,
+                                                     int64_t P, int64_t L, int to_interleaved, int64_t ny) {
+  using vec = float __attribute__((ext_vector_type(V)));
+  constexpr int kLanes = 64 / V;  // lanes per row on the contiguous side
+  __shared__ float tile[64 * 65];  // [series][step], pitch 65
+  int64_t b, by;
+  if (!xcd_tile(ny, ny * ((P + 63) / 64), b, by)) return;
+  const int64_t j0 = by * 64;
+  const int t = threadIdx.x;
+  const int c = t % kLanes, r0 = t / kLanes;  // contiguous side: V-element column, first series
+  const int q = t & 15, jr = t >> 4;          // interleaved side: series quad, first step
+  if (to_interleaved) {
+#pragma unroll
+    for (int i = 0; i < 16 / V; ++i) {
+      const int r = r0 + 4 * V * i;
+      const int64_t p = b * 64 + r, j = j0 + V * c;
+      vec v = vec(0.f);
+      if (p < P && j < L) v = *reinterpret_cast<const vec*>(src + p * L + j);
+#pragma unroll
+      for (int e = 0; e < V; ++e) tile[r * 65 + V * c + e] = v[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int jj = jr + 16 * i;
+      const int64_t j = j0 + jj;
+      if (j < L) {
+        float4 o;
+        o.x = tile[(4 * q) * 65 + jj];
+        o.y = tile[(4 * q + 1) * 65 + jj];
+        o.z = tile[(4 * q + 2) * 65 + jj];
+        o.w = tile[(4 * q + 3) * 65 + jj];
+        *reinterpret_cast<float4*>(dst + (b * L + j) * 64 + 4 * q) = o;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int jj = jr + 16 * i;
+      const int64_t j = j0 + jj;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (j < L) v = *reinterpret_cast<const float4*>(src + (b * L + j) * 64 + 4 * q);
+      tile[(4 * q) * 65 + jj] = v.x;
+      tile[(4 * q + 1) * 65 + jj] = v.y;
+      tile[(4 * q + 2) * 65 + jj] = v.z;
+      tile[(4 * q + 3) * 65 + jj] = v.w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16 / V; ++i) {
+      const int r = r0 + 4 * V * i;
+      const int64_t p = b * 64 + r, j = j0 + V * c;
+      if (p < P && j < L) {
+        vec v;
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] = tile[r * 65 + V * c + e];
+        *reinterpret_cast<vec*>(dst + p * L + j) = v;
+      }
+    }
+  }
+}
+
+// Byte k of word m of a becomes byte m of word k of the result: a 4 x 4 byte
+// transpose (four series by four steps).
+__device__ inline void transpose_bytes(const uint32_t a[4], uint32_t o[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    o[k] = ((a[0] >> (8 * k)) & 0xffu) | (((a[1] >> (8 * k)) & 0xffu) << 8) | (((a[2] >> (8 * k)) & 0xffu) << 16) |
+           (((a[3] >> (8 * k)) & 0xffu) << 24);
+}
+
+// 1-byte elements, a tile of 64 series x 256 steps held in LDS as 4-step words
+// of each series.  The series-contiguous side is read or written a word per lane
+// (64 lanes cover a series' 256 steps; L % 4 == 0), the interleaved side 16 bytes
+// per lane (16 series of one step); each lane turns four 4-series x 4-step byte
+// squares around in registers between the two.
+__global__ __launch_bounds__(256) void k_interleave1(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst,
+                                                     int64_t P, int64_t L, int to_interleaved, int64_t ny) {
+  __shared__ uint32_t tile[64 * 65];  // [series][4-step word], pitch 65 words
+  int64_t b, by;
+  if (!xcd_tile(ny, ny * ((P + 63) / 64), b, by)) return;
+  const int64_t j0 = by * 256;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int h = t & 3, cw = t >> 2;  // interleaved side: 16-series group, 4-step word of the tile
+  const int64_t Lw = L / 4, jw = j0 / 4 + lane;
+  if (to_interleaved) {
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = wv * 16 + i;
+      const int64_t p = b * 64 + r;
+      tile[r * 65 + lane] = (p < P && jw < Lw) ? s[p * Lw + jw] : 0u;
+    }
+    __syncthreads();
+    uint32_t o[4][4];  // [step k][series quad e]
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      uint32_t a[4], r[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) a[m] = tile[(16 * h + 4 * e + m) * 65 + cw];
+      transpose_bytes(a, r);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) o[k][e] = r[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t j = j0 + 4 * cw + k;
+      if (j < L) *reinterpret_cast<uint4*>(dst + (b * L + j) * 64 + 16 * h) = make_uint4(o[k][0], o[k][1], o[k][2], o[k][3]);
+    }
+  } else {
+    uint32_t in[4][4];  // [step k][series quad e]
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t j = j0 + 4 * cw + k;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (j < L) v = *reinterpret_cast<const uint4*>(src + (b * L + j) * 64 + 16 * h);
+      in[k][0] = v.x;
+      in[k][1] = v.y;
+      in[k][2] = v.z;
+      in[k][3] = v.w;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      uint32_t a[4], r[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a[k] = in[k][e];
+      transpose_bytes(a, r);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) tile[(16 * h + 4 * e + m) * 65 + cw] = r[m];
+    }
+    __syncthreads();
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = wv * 16 + i;
+      const int64_t p = b * 64 + r;
+      if (p < P && jw < Lw) d[p * Lw + jw] = tile[r * 65 + lane];
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_interleave(const void* src, void* dst, int64_t P, int64_t L, int elem_bytes, bool to_interleaved,
@@ -48,15 +209,36 @@ hipError_t launch_interleave(const void* src, void* dst, int64_t P, int64_t L, i
   if (P <= 0 || L <= 0) return hipSuccess;
   const dim3 grid((unsigned)((P + 63) / 64), (unsigned)((L + 63) / 64));
   const int dir = to_interleaved ? 1 : 0;
+  // alignment of the series-contiguous and the interleaved pointer
+  const uintptr_t ac = reinterpret_cast<uintptr_t>(to_interleaved ? src : dst);
+  const uintptr_t ai = reinterpret_cast<uintptr_t>(to_interleaved ? dst : src);
+  // the new kernels take a 1-D grid of a multiple of 8 workgroups
+  const int64_t nb = (P + 63) / 64, ny4 = (L + 63) / 64, ny1 = (L + 255) / 256;
+  const bool fits = (nb * ny4 + 7) / 8 * 8 < ((int64_t)1 << 31);
+  const dim3 g4((unsigned)((nb * ny4 + 7) / 8 * 8)), g1((unsigned)((nb * ny1 + 7) / 8 * 8));
   switch (elem_bytes) {
     case 1:
-      hipLaunchKernelGGL(k_interleave<uint8_t>, grid, dim3(256), 0, stream, static_cast<const uint8_t*>(src),
-                         static_cast<uint8_t*>(dst), P, L, dir);
+      if (fits && L % 4 == 0 && ac % 4 == 0 && ai % 16 == 0) {
+        hipLaunchKernelGGL(k_interleave1, g1, dim3(256), 0, stream, static_cast<const uint8_t*>(src),
+                           static_cast<uint8_t*>(dst), P, L, dir, ny1);
+      } else {
+        hipLaunchKernelGGL(k_interleave<uint8_t>, grid, dim3(256), 0, stream, static_cast<const uint8_t*>(src),
+                           static_cast<uint8_t*>(dst), P, L, dir);
+      }
       break;
-    case 4:
-      hipLaunchKernelGGL(k_interleave<float>, grid, dim3(256), 0, stream, static_cast<const float*>(src),
-                         static_cast<float*>(dst), P, L, dir);
+    case 4: {
+      const float* s4 = static_cast<const float*>(src);
+      float* d4 = static_cast<float*>(dst);
+      if (!fits || ai % 16 != 0)
+        hipLaunchKernelGGL(k_interleave<float>, grid, dim3(256), 0, stream, s4, d4, P, L, dir);
+      else if (L % 4 == 0 && ac % 16 == 0)
+        hipLaunchKernelGGL(k_interleave4<4>, g4, dim3(256), 0, stream, s4, d4, P, L, dir, ny4);
+      else if (L % 2 == 0 && ac % 8 == 0)
+        hipLaunchKernelGGL(k_interleave4<2>, g4, dim3(256), 0, stream, s4, d4, P, L, dir, ny4);
+      else
+        hipLaunchKernelGGL(k_interleave4<1>, g4, dim3(256), 0, stream, s4, d4, P, L, dir, ny4);
       break;
+    }
     case 8:
       hipLaunchKernelGGL(k_interleave<double>, grid, dim3(256), 0, stream, static_cast<const double*>(src),
                          static_cast<double*>(dst), P, L, dir);
