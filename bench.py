@@ -512,15 +512,16 @@ def bench_hetero(args):
     from paper_2604_00048_amd import synth, whs
     dev = torch.device("cuda:0")
     d, S, P, T = args.d, args.interleave, args.P, args.T
+    f64 = args.dtype == "f64"
+    dt, esz = (torch.float64, 8) if f64 else (torch.float32, 4)
     t_gen = time.perf_counter()
-    pk = synth.generate_packed("heteroscedastic", P, S=S, dtype=torch.float32, device=dev, chunk=8192, T=T, d=d)
-    g = torch.randn(pk.x.shape, generator=torch.Generator(device=dev).manual_seed(7), device=dev,
-                    dtype=torch.float32)
+    pk = synth.generate_packed("heteroscedastic", P, S=S, dtype=dt, device=dev, chunk=8192, T=T, d=d)
+    g = torch.randn(pk.x.shape, generator=torch.Generator(device=dev).manual_seed(7), device=dev, dtype=dt)
     z = torch.empty_like(pk.x)
     gx = torch.empty_like(pk.x)
     gl = torch.empty_like(pk.lam)
     info = torch.empty(P, dtype=torch.int32, device=dev)
-    desc = whs.make_desc(P, T, d, 1, S, whs.WHS_F32, whs.WHS_LAMBDA_PER_DIFF)
+    desc = whs.make_desc(P, T, d, 1, S, whs.WHS_F64 if f64 else whs.WHS_F32, whs.WHS_LAMBDA_PER_DIFF)
     nws = whs.workspace_bytes(desc)
     if S == 1 and not args.in_place:
         # series-contiguous: the workspace that runs the interleaved kernels on copies
@@ -565,11 +566,11 @@ def bench_hetero(args):
 
     print(f"# timed {K} steps: {total_ms / K:.3f} ms per step", file=sys.stderr, flush=True)
     copy_gbs = copy_ceiling(dev)
-    fb, bb = alg_bytes(T, d, 1, 4, True, args.w_bits)
+    fb, bb = alg_bytes(T, d, 1, esz, True, args.w_bits)
     bwd_gbs = bb * P / (bwd_ms * 1e-3) / 1e9
     fwd_gbs = fb * P / (fwd_ms * 1e-3) / 1e9
     step_gbs = (fb + bb) * P / (ms_step * 1e-3) / 1e9
-    workload = f"heteroscedastic P={P} T={T} d={d} C=1" + (" w bits" if args.w_bits else "")
+    workload = f"heteroscedastic P={P} T={T} d={d} C=1" + (" w bits" if args.w_bits else "") + (" f64" if f64 else "")
     traffic = measured_traffic("whs_backward", workload)
     out = {
         "metric": METRIC,
@@ -586,9 +587,9 @@ def bench_hetero(args):
         "data": "synthetic",
         "config": {
             "workload": f"heteroscedastic smoother fwd+bwd: P={P} series, T={T} daily steps, d={d}, C=1 band, "
-                        "per-difference lambda (log10 GP field), FP32 storage / FP64 arithmetic"
+                        f"per-difference lambda (log10 GP field), {'FP64' if f64 else 'FP32'} storage / FP64 arithmetic"
                         + (", 0/1 weights packed eight to a byte" if args.w_bits else ""),
-            "P": P, "T": T, "d": d, "C": 1, "storage": "f32", "interleave": S,
+            "P": P, "T": T, "d": d, "C": 1, "storage": args.dtype, "interleave": S,
             **({"w_format": "bits"} if args.w_bits else {}),
             **({"contiguous_path": "in place" if args.in_place else "interleaved copies"} if S == 1 else {}),
         },

@@ -91,9 +91,10 @@ Staged staged_sizes(const whs_desc* d) {
 }
 
 bool use_staged(const whs_desc* d, const double* factor, size_t ws_bytes) {
-  // the transposes take rows of up to 65535 x 64 elements (second grid dimension)
+  // the transposes' grids bound the rows and the series count
   return d->interleave == 1 && !factor && d->n_series > 0 && d->n_series < ((int64_t)1 << 31) &&
-         (int64_t)d->T * d->n_rhs <= (int64_t)65535 * 64 && ws_bytes >= staged_sizes(d).total();
+         whs::interleave_fits(d->n_series, (int64_t)d->T * d->n_rhs, (int)elem(d)) &&
+         ws_bytes >= staged_sizes(d).total();
 }
 
 struct Slots {
@@ -222,7 +223,9 @@ size_t whs_workspace_bytes(const whs_desc* desc) {
 
 size_t whs_interleave_workspace_bytes(const whs_desc* desc) {
   if (check_desc(desc) != WHS_OK || desc->n_series == 0 || desc->interleave != 1) return 0;
-  if (desc->n_series >= ((int64_t)1 << 31) || (int64_t)desc->T * desc->n_rhs > (int64_t)65535 * 64) return 0;
+  if (desc->n_series >= ((int64_t)1 << 31) ||
+      !whs::interleave_fits(desc->n_series, (int64_t)desc->T * desc->n_rhs, (int)elem(desc)))
+    return 0;
   return staged_sizes(desc).total();
 }
 

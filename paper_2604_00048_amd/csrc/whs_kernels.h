@@ -32,6 +32,9 @@ hipError_t launch_factor(const LaunchDesc& L, hipStream_t stream);
 // (P, L) series-contiguous <-> (ceil(P/64), L, 64) interleaved, elements of 1, 4 or 8 bytes
 hipError_t launch_interleave(const void* src, void* dst, int64_t P, int64_t L, int elem_bytes, bool to_interleaved,
                              hipStream_t stream);
+// whether launch_interleave takes (P, L') with L' <= L, for elements of at most
+// elem_bytes (4 or 8) and any alignment
+bool interleave_fits(int64_t P, int64_t L, int elem_bytes);
 // coefficient table of D from sample times: coef[k][j] = d! / prod_{m != j} (t[k+j] - t[k+m])
 hipError_t launch_diff_coef(const double* times, int T, int D, double* coef, hipStream_t stream);
 

@@ -57,66 +57,70 @@ __device__ inline bool xcd_tile(int64_t n_step_tiles, int64_t n_tiles, int64_t& 
   return true;
 }
 
-// 4-byte elements, a tile of 64 series x 64 steps.  The series-contiguous side
-// is read or written V elements per access (its rows start V-aligned: L % V == 0),
-// the interleaved side four (16 bytes: a quarter of a step's 64-series row).
-template <int V>
-__global__ __launch_bounds__(256) void k_interleave4(const float* __restrict__ src, float* __restrict__ dst,
-                                                     int64_t P, int64_t L, int to_interleaved, int64_t ny) {
-  using vec = float __attribute__((ext_vector_type(V)));
-  constexpr int kLanes = 64 / V;  // lanes per row on the contiguous side
-  __shared__ float tile[64 * 65];  // [series][step], pitch 65
+// 4- and 8-byte elements, a tile of 64 series x TJ steps (a 256-byte piece of
+// each series row).  The series-contiguous side is read or written V elements per
+// access (its rows start V-aligned: L % V == 0), the interleaved side 16 bytes per
+// access.
+template <typename E, int V>
+__global__ __launch_bounds__(256) void k_interleave_wide(const E* __restrict__ src, E* __restrict__ dst, int64_t P,
+                                                         int64_t L, int to_interleaved, int64_t ny) {
+  constexpr int TJ = 256 / (int)sizeof(E);  // steps per tile
+  constexpr int IV = 16 / (int)sizeof(E);   // elements per access on the interleaved side
+  constexpr int kLanes = TJ / V;            // lanes per series row on the contiguous side
+  constexpr int kRows = 256 / kLanes;       // series rows per pass there
+  constexpr int kILanes = 64 / IV;          // lanes per step row on the interleaved side
+  constexpr int kIRows = 256 / kILanes;     // step rows per pass there
+  constexpr int kPitch = TJ + 1;
+  using vec = E __attribute__((ext_vector_type(V)));
+  using ivec = E __attribute__((ext_vector_type(IV)));
+  __shared__ E tile[64 * kPitch];  // [series][step]
   int64_t b, by;
   if (!xcd_tile(ny, ny * ((P + 63) / 64), b, by)) return;
-  const int64_t j0 = by * 64;
+  const int64_t j0 = by * TJ;
   const int t = threadIdx.x;
-  const int c = t % kLanes, r0 = t / kLanes;  // contiguous side: V-element column, first series
-  const int q = t & 15, jr = t >> 4;          // interleaved side: series quad, first step
+  const int c = t % kLanes, r0 = t / kLanes;   // contiguous side: V-element column, first series
+  const int q = t % kILanes, jr = t / kILanes;  // interleaved side: series group, first step
   if (to_interleaved) {
 #pragma unroll
-    for (int i = 0; i < 16 / V; ++i) {
-      const int r = r0 + 4 * V * i;
+    for (int i = 0; i < 64 / kRows; ++i) {
+      const int r = r0 + kRows * i;
       const int64_t p = b * 64 + r, j = j0 + V * c;
-      vec v = vec(0.f);
+      vec v = vec(E(0));
       if (p < P && j < L) v = *reinterpret_cast<const vec*>(src + p * L + j);
 #pragma unroll
-      for (int e = 0; e < V; ++e) tile[r * 65 + V * c + e] = v[e];
+      for (int e = 0; e < V; ++e) tile[r * kPitch + V * c + e] = v[e];
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int jj = jr + 16 * i;
+    for (int i = 0; i < TJ / kIRows; ++i) {
+      const int jj = jr + kIRows * i;
       const int64_t j = j0 + jj;
       if (j < L) {
-        float4 o;
-        o.x = tile[(4 * q) * 65 + jj];
-        o.y = tile[(4 * q + 1) * 65 + jj];
-        o.z = tile[(4 * q + 2) * 65 + jj];
-        o.w = tile[(4 * q + 3) * 65 + jj];
-        *reinterpret_cast<float4*>(dst + (b * L + j) * 64 + 4 * q) = o;
+        ivec o;
+#pragma unroll
+        for (int m = 0; m < IV; ++m) o[m] = tile[(IV * q + m) * kPitch + jj];
+        *reinterpret_cast<ivec*>(dst + (b * L + j) * 64 + IV * q) = o;
       }
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int jj = jr + 16 * i;
+    for (int i = 0; i < TJ / kIRows; ++i) {
+      const int jj = jr + kIRows * i;
       const int64_t j = j0 + jj;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (j < L) v = *reinterpret_cast<const float4*>(src + (b * L + j) * 64 + 4 * q);
-      tile[(4 * q) * 65 + jj] = v.x;
-      tile[(4 * q + 1) * 65 + jj] = v.y;
-      tile[(4 * q + 2) * 65 + jj] = v.z;
-      tile[(4 * q + 3) * 65 + jj] = v.w;
+      ivec v = ivec(E(0));
+      if (j < L) v = *reinterpret_cast<const ivec*>(src + (b * L + j) * 64 + IV * q);
+#pragma unroll
+      for (int m = 0; m < IV; ++m) tile[(IV * q + m) * kPitch + jj] = v[m];
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16 / V; ++i) {
-      const int r = r0 + 4 * V * i;
+    for (int i = 0; i < 64 / kRows; ++i) {
+      const int r = r0 + kRows * i;
       const int64_t p = b * 64 + r, j = j0 + V * c;
       if (p < P && j < L) {
         vec v;
 #pragma unroll
-        for (int e = 0; e < V; ++e) v[e] = tile[r * 65 + V * c + e];
+        for (int e = 0; e < V; ++e) v[e] = tile[r * kPitch + V * c + e];
         *reinterpret_cast<vec*>(dst + p * L + j) = v;
       }
     }
@@ -204,6 +208,18 @@ __global__ __launch_bounds__(256) void k_interleave1(const uint8_t* __restrict__
 
 }  // namespace
 
+// A launch counts at most 2^32 - 1 work-items.
+constexpr int64_t kMaxGroups = (int64_t)0xffffffff / 256;
+
+bool interleave_fits(int64_t P, int64_t L, int elem_bytes) {
+  const int64_t nb = (P + 63) / 64;
+  if (P <= 0 || L <= 0) return true;
+  // the wide kernels' 1-D grid (tiles of 256 bytes of a series row), and the
+  // one-element kernel's 2-D grid
+  const int64_t steps = elem_bytes == 8 ? 32 : 64;
+  return (nb * ((L + steps - 1) / steps) + 7) / 8 * 8 <= kMaxGroups && nb <= kMaxGroups && (L + 63) / 64 <= 65535;
+}
+
 hipError_t launch_interleave(const void* src, void* dst, int64_t P, int64_t L, int elem_bytes, bool to_interleaved,
                              hipStream_t stream) {
   if (P <= 0 || L <= 0) return hipSuccess;
@@ -212,37 +228,57 @@ hipError_t launch_interleave(const void* src, void* dst, int64_t P, int64_t L, i
   // alignment of the series-contiguous and the interleaved pointer
   const uintptr_t ac = reinterpret_cast<uintptr_t>(to_interleaved ? src : dst);
   const uintptr_t ai = reinterpret_cast<uintptr_t>(to_interleaved ? dst : src);
-  // the new kernels take a 1-D grid of a multiple of 8 workgroups
-  const int64_t nb = (P + 63) / 64, ny4 = (L + 63) / 64, ny1 = (L + 255) / 256;
-  const bool fits = (nb * ny4 + 7) / 8 * 8 < ((int64_t)1 << 31);
-  const dim3 g4((unsigned)((nb * ny4 + 7) / 8 * 8)), g1((unsigned)((nb * ny1 + 7) / 8 * 8));
+  // the wide kernels take a 1-D grid of a multiple of 8 workgroups
+  const int64_t nb = (P + 63) / 64;
+  auto grid1 = [&](int64_t steps_per_tile, int64_t& ny) {
+    ny = (L + steps_per_tile - 1) / steps_per_tile;
+    return (nb * ny + 7) / 8 * 8;
+  };
+  const bool narrow_fits = nb <= kMaxGroups && (L + 63) / 64 <= 65535;
+  int64_t ny = 0, n = 0;
   switch (elem_bytes) {
     case 1:
-      if (fits && L % 4 == 0 && ac % 4 == 0 && ai % 16 == 0) {
-        hipLaunchKernelGGL(k_interleave1, g1, dim3(256), 0, stream, static_cast<const uint8_t*>(src),
-                           static_cast<uint8_t*>(dst), P, L, dir, ny1);
-      } else {
+      n = grid1(256, ny);
+      if (n <= kMaxGroups && L % 4 == 0 && ac % 4 == 0 && ai % 16 == 0) {
+        hipLaunchKernelGGL(k_interleave1, dim3((unsigned)n), dim3(256), 0, stream, static_cast<const uint8_t*>(src),
+                           static_cast<uint8_t*>(dst), P, L, dir, ny);
+      } else if (narrow_fits) {
         hipLaunchKernelGGL(k_interleave<uint8_t>, grid, dim3(256), 0, stream, static_cast<const uint8_t*>(src),
                            static_cast<uint8_t*>(dst), P, L, dir);
+      } else {
+        return hipErrorInvalidValue;
       }
       break;
     case 4: {
       const float* s4 = static_cast<const float*>(src);
       float* d4 = static_cast<float*>(dst);
-      if (!fits || ai % 16 != 0)
+      n = grid1(64, ny);
+      const dim3 g((unsigned)n);
+      if (n > kMaxGroups || ai % 16 != 0) {
+        if (!narrow_fits) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_interleave<float>, grid, dim3(256), 0, stream, s4, d4, P, L, dir);
-      else if (L % 4 == 0 && ac % 16 == 0)
-        hipLaunchKernelGGL(k_interleave4<4>, g4, dim3(256), 0, stream, s4, d4, P, L, dir, ny4);
+      } else if (L % 4 == 0 && ac % 16 == 0)
+        hipLaunchKernelGGL((k_interleave_wide<float, 4>), g, dim3(256), 0, stream, s4, d4, P, L, dir, ny);
       else if (L % 2 == 0 && ac % 8 == 0)
-        hipLaunchKernelGGL(k_interleave4<2>, g4, dim3(256), 0, stream, s4, d4, P, L, dir, ny4);
+        hipLaunchKernelGGL((k_interleave_wide<float, 2>), g, dim3(256), 0, stream, s4, d4, P, L, dir, ny);
       else
-        hipLaunchKernelGGL(k_interleave4<1>, g4, dim3(256), 0, stream, s4, d4, P, L, dir, ny4);
+        hipLaunchKernelGGL((k_interleave_wide<float, 1>), g, dim3(256), 0, stream, s4, d4, P, L, dir, ny);
       break;
     }
-    case 8:
-      hipLaunchKernelGGL(k_interleave<double>, grid, dim3(256), 0, stream, static_cast<const double*>(src),
-                         static_cast<double*>(dst), P, L, dir);
+    case 8: {
+      const double* s8 = static_cast<const double*>(src);
+      double* d8 = static_cast<double*>(dst);
+      n = grid1(32, ny);
+      const dim3 g((unsigned)n);
+      if (n > kMaxGroups || ai % 16 != 0) {
+        if (!narrow_fits) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_interleave<double>, grid, dim3(256), 0, stream, s8, d8, P, L, dir);
+      } else if (L % 2 == 0 && ac % 16 == 0)
+        hipLaunchKernelGGL((k_interleave_wide<double, 2>), g, dim3(256), 0, stream, s8, d8, P, L, dir, ny);
+      else
+        hipLaunchKernelGGL((k_interleave_wide<double, 1>), g, dim3(256), 0, stream, s8, d8, P, L, dir, ny);
       break;
+    }
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

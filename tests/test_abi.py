@@ -180,6 +180,13 @@ def test_interleave_workspace_size():
         assert n >= whs.workspace_bytes(desc)
     assert L.whs_interleave_workspace_bytes(ctypes.byref(whs.make_desc(100, 365, 2, 1, 64, 0, 1))) == 0
     assert L.whs_interleave_workspace_bytes(ctypes.byref(whs.make_desc(0, 365, 2, 1, 1, 0, 1))) == 0
+    # the copies' grids count at most 2^32 - 1 work-items of 256 per workgroup, one
+    # workgroup per 64 series and 256 bytes of their rows: beyond that the
+    # contiguous layout is refused this way (0), not launched
+    big = lambda P, T, dt: L.whs_interleave_workspace_bytes(ctypes.byref(whs.make_desc(P, T, 2, 1, 1, dt, 1)))  # noqa: E731
+    assert big(2 ** 30, 365, 0) == 0                    # 2^24 series blocks
+    assert big(2 ** 24, 3288, 1) == 0 and big(2 ** 24, 3288, 0) > 0   # FP64 rows take twice the tiles
+    assert big(64 * (2 ** 24 - 1), 31, 0) == 0 and big(64 * (2 ** 24 - 8), 31, 0) > 0
 
 
 def test_backward_validation():
