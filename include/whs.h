@@ -110,8 +110,10 @@ size_t whs_workspace_bytes(const whs_desc* desc);
 /* Series-contiguous inputs (interleave = 1): bytes of a workspace that also
  * holds interleaved copies of the call's arrays (x or g, z, grad_x, w, and
  * lambda / grad_lambda when per difference row) plus the checkpoints of the
- * interleaved kernels; 0 for interleave != 1, P = 0, P >= 2^31 or T*C >
- * 65535*64 (then only the in-place kernels apply).  Given at least this
+ * interleaved kernels; 0 for interleave != 1, P = 0, or where the copies'
+ * grids would not fit a launch (T*C > 65535*64, or ceil(P/64) * ceil(T*C/k)
+ * above 2^24 - 8 with k = 64 steps in FP32 and 32 in FP64); then only the
+ * in-place kernels apply.  Given at least this
  * much, whs_solve, whs_backward, whs_solve_coef and whs_backward_coef on
  * interleave 1 (fused path, factor NULL) copy their inputs into the
  * interleaved layout with a tiled transpose, run the throughput kernels and
@@ -119,9 +121,9 @@ size_t whs_workspace_bytes(const whs_desc* desc);
  * and band count, and the uneven-date calls then accept interleave 1 too.
  * With less (but at least whs_workspace_bytes), interleave-1 calls run the
  * kernels that read the contiguous layout in place: for one band and d <= 2
- * the partition kernel (256 lanes per series), which is the faster choice for
- * small batches (below about 10,000 series of 3288 steps, where one lane per
- * series leaves most of the GPU idle). */
+ * the partition kernel (256 lanes per series, for P < 2^24), which is the
+ * faster choice for small batches (below about 10,000 series of 3288 steps,
+ * where one lane per series leaves most of the GPU idle). */
 size_t whs_interleave_workspace_bytes(const whs_desc* desc);
 
 /* Bytes of the factor array whs_factor writes: P_pad * (d+1) * T * 8. */

@@ -671,7 +671,9 @@ hipError_t chunk_d(const LaunchDesc& L, hipStream_t stream) {
 // D is the daily-grid operator, and a series fits 256 chunks of 13 samples.
 bool chunk_path(const LaunchDesc& L) {
   if (L.S != 1 || L.C != 1 || L.D < 1 || L.D > 2 || L.fac || L.coef) return false;
-  if (L.T > kThreads * kMmax || L.P < 1 || L.P >= ((int64_t)1 << 31)) return false;
+  // one workgroup per series; a grid counts at most 2^32 - 1 work-items, so larger
+  // batches take the one-lane kernel
+  if (L.T > kThreads * kMmax || L.P < 1 || L.P > (int64_t)0xffffffff / kThreads) return false;
   const size_t lds = L.D == 1 ? chunk_lds_bytes<1>(L.T, L.f64 ? 8 : 4, L.perdiff)
                               : chunk_lds_bytes<2>(L.T, L.f64 ? 8 : 4, L.perdiff);
   return lds <= 64 * 1024;
