@@ -4,8 +4,11 @@ results must be bit-identical to the same call on interleaved tensors (the same
 kernels on the same values), which the oracle parity of the interleaved path
 then covers: every order, several bands (beyond the partition kernel's one),
 both weight kinds, both storage types, the adjoint, a series count that is not
-a multiple of 64, and the uneven-date calls, which take the contiguous layout
-only this way."""
+a multiple of 64, the uneven-date calls, which take the contiguous layout
+only this way, and arrays and workspaces whose addresses make the copies take
+their narrower accesses."""
+
+import ctypes
 
 import numpy as np
 import pytest
@@ -65,3 +68,42 @@ def test_uneven_dates_contiguous_match_interleaved(d, C):
     # without the larger workspace the uneven-date calls refuse the contiguous layout
     with pytest.raises(RuntimeError):
         whs.whs_solve(x1, w1, l1, d, P, coef=coef, staged=False)
+
+
+def _at_offset(t, k):
+    """The values of t at a storage offset of k elements (the data pointer then
+    loses its 16-byte alignment unless k elements make 16 bytes)."""
+    buf = torch.zeros(t.numel() + k, dtype=t.dtype, device=t.device)
+    v = buf[k:].view(t.shape)
+    v.copy_(t)
+    return v
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("k_x,k_w,ws_off", [(1, 1, 0), (2, 4, 0), (0, 0, 8), (1, 3, 8)])
+def test_contiguous_calls_at_unaligned_addresses(dt, k_x, k_w, ws_off):
+    # where a contiguous array does not start 16-byte aligned the copies take
+    # narrower accesses, and where the workspace (8-byte aligned is allowed)
+    # puts the interleaved copies off 16 bytes they take one element per
+    # access: the same results, bit for bit
+    dtype = DT[dt]
+    P, T, d = 70, 300, 2
+    x, w, lam = random_case(P, T, d, per_diff=True, seed=9 + k_x, dtype=dtype)
+    (x64, w64, l64), (x1, w1, l1) = both_layouts(x, w, lam, dtype)
+    xo, wo, lo = _at_offset(x1, k_x), _at_offset(w1, k_w), _at_offset(l1, k_x)
+    desc = whs.make_desc(P, T, d, 1, 1, whs.WHS_F64 if dt == "f64" else whs.WHS_F32, whs.WHS_LAMBDA_PER_DIFF)
+    n = int(whs.lib().whs_interleave_workspace_bytes(ctypes.byref(desc)))
+    assert n > 0
+    ws = torch.empty(n + 256, dtype=torch.uint8, device="cuda")[ws_off:ws_off + n]
+    z64, i64 = whs.whs_solve(x64, w64, l64, d, P)
+    zo, io = whs.whs_solve(xo, wo, lo, d, P, z=_at_offset(torch.zeros_like(x1), k_x), workspace=ws)
+    g = torch.tensor(np.random.default_rng(3).normal(size=x.shape), dtype=dtype)
+    g64, g1 = synth.pack_series(g, 64).cuda(), _at_offset(synth.pack_series(g, 1).cuda(), k_x)
+    gx64, gl64, _ = whs.whs_backward(w64, l64, z64, g64, d, P)
+    gxo, glo = _at_offset(torch.zeros_like(x1), k_x), _at_offset(torch.zeros_like(l1), k_x)
+    whs.whs_backward(wo, lo, zo, g1, d, P, grad_x=gxo, grad_lambda=glo, workspace=ws)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(io.cpu().numpy(), i64.cpu().numpy())
+    np.testing.assert_array_equal(from_device_series(zo, P), from_device_series(z64, P))
+    np.testing.assert_array_equal(from_device_series(gxo, P), from_device_series(gx64, P))
+    np.testing.assert_array_equal(from_device_rows(glo, P), from_device_rows(gl64, P))
