@@ -3,9 +3,10 @@
 // (p, j) sits at p*L + j in one and at ((p/64)*L + j)*64 + p%64 in the other.
 // A workgroup moves one tile through LDS so both sides are read and written in
 // whole rows.  Interleaving zero-fills the slots of the last block that hold no
-// series.  4-byte and 1-byte elements take wide accesses where the rows allow
-// them; other cases (8-byte elements, rows whose starts are not aligned) take
-// one element per access.
+// series.  Elements of 1, 4 and 8 bytes take wide accesses where the pointers
+// and row lengths allow them; one element per access otherwise (an interleaved
+// copy not 16-byte aligned, byte rows whose start or length is not a multiple
+// of 4).
 #include <hip/hip_runtime.h>
 
 #include "whs_kernels.h"
