@@ -304,13 +304,17 @@ def bench_gcv(args):
     info = torch.empty(P, dtype=torch.int32, device=dev)
     z = torch.empty_like(pk.x)
     desc = whs.make_desc(P, T, d, 1, S, whs.WHS_F64 if dtype == torch.float64 else whs.WHS_F32, whs.WHS_LAMBDA_SCALAR)
-    ws = torch.empty(whs.workspace_bytes(desc), dtype=torch.uint8, device=dev)
+    nws = whs.workspace_bytes(desc)
+    if S == 1:
+        # series-contiguous: one workspace for the copies of both calls
+        nws = max(nws, int(whs.lib().whs_interleave_workspace_bytes(ctypes.byref(desc))))
+    ws = torch.empty(max(nws, 8), dtype=torch.uint8, device=dev)
     ev = _events(2 * args.steps + 2)
 
     def step(k=None):
         if k is not None:
             ev[2 * k].record()
-        whs.whs_gcv(pk.x, pk.w, grid, d, P, lambda_best=lam_best, info=info)
+        whs.whs_gcv(pk.x, pk.w, grid, d, P, lambda_best=lam_best, info=info, workspace=ws)
         if k is not None:
             ev[2 * k + 1].record()
         whs.whs_solve(pk.x, pk.w, lam_best, d, P, z=z, workspace=ws)
@@ -334,7 +338,8 @@ def bench_gcv(args):
         "config": {"workload": f"plain form: GCV choice of a scalar weight over 21 grid values, then the solve at "
                                f"it: P={P} series, T={T} daily steps, d={d}, one band, "
                                f"{args.dtype.upper()} storage / FP64 arithmetic",
-                   "P": P, "T": T, "d": d, "n_grid": grid.numel(), "storage": args.dtype},
+                   "P": P, "T": T, "d": d, "n_grid": grid.numel(), "storage": args.dtype, "interleave": S,
+                   **({"contiguous_path": "interleaved copies"} if S == 1 else {})},
         "roofline": {"bound": "alu", "kernel": "whs_gcv", "achieved": tf, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": tf / PEAK_FP64_TFLOPS, "traffic": None,
                      "flops_per_series_step_grid_value": GCV_FLOPS_PER_STEP[d], "ms_per_launch": gcv_ms},

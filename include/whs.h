@@ -198,12 +198,16 @@ int whs_backward(const whs_desc* desc, const uint8_t* w, const void* lambda,
  * RSS = sum w x^2 minus d/deps of b^T Omega^{-1} b), equal to the sums above
  * up to rounding.  lambda_best[p] is the grid value of the first minimum
  * (NaN if every grid value failed).  Requires n_rhs == 1, lambda_kind ==
- * SCALAR (it describes lambda_best), interleave a multiple of 64
+ * SCALAR (it describes lambda_best), interleave a multiple of 64 or 1
  * (WHS_ERR_UNSUPPORTED otherwise).  grid: device FP64[n_grid], n_grid >= 1.
  * scores: device FP64[P][n_grid] or NULL.  info: 0 if some grid value
  * succeeded, else the first grid value's failure code.  x is read at w = 1
- * only.  No workspace is used: whs_gcv_workspace_bytes returns 0 and
- * workspace may be NULL.
+ * only.  Interleaves that are a multiple of 64 use no workspace
+ * (whs_gcv_workspace_bytes returns 0; workspace may be NULL).  Interleave 1
+ * copies x and w into the interleaved layout in a workspace of at least
+ * whs_gcv_workspace_bytes(desc) bytes (8-byte aligned; WHS_ERR_WORKSPACE
+ * otherwise), which returns 0, and the call WHS_ERR_UNSUPPORTED, where
+ * whs_interleave_workspace_bytes would (the copies do not fit a launch).
  */
 size_t whs_gcv_workspace_bytes(const whs_desc* desc);
 int whs_gcv(const whs_desc* desc, const uint8_t* w, const void* x, const double* grid, int32_t n_grid,
@@ -255,10 +259,13 @@ int whs_backward_coef(const whs_desc* desc, const double* coef, const uint8_t* w
  *   Sigma[t, t]   = 1/Dp[t] - sum_i L[t+i, t] Sigma[t+i, t].
  * var: device, storage dtype, series layout with C = 1 (like x); lambda as
  * in whs_solve (both kinds).  Requires n_rhs == 1 (WHS_ERR_ARG otherwise)
- * and interleave a multiple of 64 (WHS_ERR_UNSUPPORTED otherwise).  Failed
- * series (info != 0) get NaN.  All outputs are written on `stream`; the
- * caller owns every buffer.  The workspace size is
- * whs_variance_workspace_bytes(desc).
+ * and interleave a multiple of 64 or 1 (WHS_ERR_UNSUPPORTED otherwise).
+ * Interleave 1 copies w and a per-difference lambda into the interleaved
+ * layout, runs the interleaved kernel and copies var back, all in the
+ * workspace (WHS_ERR_UNSUPPORTED where the copies do not fit a launch, as for
+ * whs_interleave_workspace_bytes).  Failed series (info != 0) get NaN.  All
+ * outputs are written on `stream`; the caller owns every buffer.  The
+ * workspace size is whs_variance_workspace_bytes(desc).
  */
 size_t whs_variance_workspace_bytes(const whs_desc* desc);
 int whs_variance(const whs_desc* desc, const uint8_t* w, const void* lambda, void* var, int32_t* info,

@@ -90,11 +90,35 @@ Staged staged_sizes(const whs_desc* d) {
   return s;
 }
 
+// Whether a series-contiguous call can run the interleaved kernels on copies:
+// the copies' grids fit a launch, and one block of 64 series stays within the
+// interleaved kernels' 32-bit ranges.
+bool staged_fits(const whs_desc* d) {
+  if (d->interleave != 1 || d->n_series <= 0 || d->n_series >= ((int64_t)1 << 31)) return false;
+  if (!whs::interleave_fits(d->n_series, (int64_t)d->T * d->n_rhs, (int)elem(d))) return false;
+  whs_desc d64 = *d;
+  d64.interleave = 64;
+  return block_ranges_fit(&d64);
+}
+
 bool use_staged(const whs_desc* d, const double* factor, size_t ws_bytes) {
-  // the transposes' grids bound the rows and the series count
-  return d->interleave == 1 && !factor && d->n_series > 0 && d->n_series < ((int64_t)1 << 31) &&
-         whs::interleave_fits(d->n_series, (int64_t)d->T * d->n_rhs, (int)elem(d)) &&
-         ws_bytes >= staged_sizes(d).total();
+  return !factor && staged_fits(d) && ws_bytes >= staged_sizes(d).total();
+}
+
+// GCV on copies: slots for x and w
+size_t gcv_staged_bytes(const whs_desc* d) {
+  const size_t nb = (size_t)((d->n_series + 63) / 64);
+  return up256(nb * 64 * (size_t)d->T * elem(d)) + up256(nb * 64 * (size_t)d->T);
+}
+
+// The variance on copies: slots for w, lambda (per difference row), var, then
+// the interleaved kernel's checkpoints
+size_t var_staged_bytes(const whs_desc* d) {
+  const size_t nb = (size_t)((d->n_series + 63) / 64);
+  const size_t e = elem(d);
+  const size_t lam = d->lambda_kind == WHS_LAMBDA_PER_DIFF ? up256(nb * 64 * (size_t)(d->T - d->d) * e) : 0;
+  return up256(nb * 64 * (size_t)d->T) + lam + up256(nb * 64 * (size_t)d->T * e) +
+         whs::var_checkpoint_bytes(d->n_series, 64, d->T, d->d);
 }
 
 struct Slots {
@@ -223,9 +247,7 @@ size_t whs_workspace_bytes(const whs_desc* desc) {
 
 size_t whs_interleave_workspace_bytes(const whs_desc* desc) {
   if (check_desc(desc) != WHS_OK || desc->n_series == 0 || desc->interleave != 1) return 0;
-  if (desc->n_series >= ((int64_t)1 << 31) ||
-      !whs::interleave_fits(desc->n_series, (int64_t)desc->T * desc->n_rhs, (int)elem(desc)))
-    return 0;
+  if (!staged_fits(desc)) return 0;
   return staged_sizes(desc).total();
 }
 
@@ -388,7 +410,11 @@ int whs_backward_coef(const whs_desc* desc, const double* coef, const uint8_t* w
   return hip_status(whs::launch_backward(L, static_cast<hipStream_t>(stream)));
 }
 
-size_t whs_gcv_workspace_bytes(const whs_desc*) { return 0; }  // one forward sweep, nothing kept
+size_t whs_gcv_workspace_bytes(const whs_desc* desc) {
+  // one forward sweep, nothing kept; series-contiguous calls copy x and w
+  if (check_desc(desc) != WHS_OK || !staged_fits(desc)) return 0;
+  return gcv_staged_bytes(desc);
+}
 
 int whs_gcv(const whs_desc* desc, const uint8_t* w, const void* x, const double* grid, int32_t n_grid,
             void* lambda_best, double* scores, int32_t* info, void* workspace, size_t workspace_bytes,
@@ -397,15 +423,20 @@ int whs_gcv(const whs_desc* desc, const uint8_t* w, const void* x, const double*
   if (st != WHS_OK) return st;
   if (desc->w_format == WHS_W_BITS) return WHS_ERR_UNSUPPORTED;
   if (desc->n_rhs != 1 || desc->lambda_kind != WHS_LAMBDA_SCALAR) return WHS_ERR_UNSUPPORTED;
-  if (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31)) return WHS_ERR_UNSUPPORTED;
+  if ((desc->interleave % 64 != 0 && desc->interleave != 1) || desc->n_series >= ((int64_t)1 << 31))
+    return WHS_ERR_UNSUPPORTED;
   if (n_grid < 1) return WHS_ERR_ARG;
   if (desc->n_series == 0) return WHS_OK;
   if (!w || !x || !grid || !lambda_best) return WHS_ERR_ARG;
   const size_t e = elem(desc);
   if (!aligned(x, e) || !aligned(lambda_best, e) || !aligned(grid, 8) || !aligned(scores, 8) || !aligned(info, 4))
     return WHS_ERR_ARG;
-  (void)workspace;
-  (void)workspace_bytes;
+  const bool staged = desc->interleave == 1;
+  if (staged) {
+    if (!staged_fits(desc)) return WHS_ERR_UNSUPPORTED;
+    if (!workspace || workspace_bytes < gcv_staged_bytes(desc) || !aligned(workspace, 8)) return WHS_ERR_WORKSPACE;
+  }
+  const hipStream_t s = static_cast<hipStream_t>(stream);
   whs::GcvLaunch L{};
   L.P = desc->n_series;
   L.T = desc->T;
@@ -419,11 +450,23 @@ int whs_gcv(const whs_desc* desc, const uint8_t* w, const void* x, const double*
   L.lam_best = lambda_best;
   L.scores = scores;
   L.info = info;
-  return hip_status(whs::launch_gcv(L, static_cast<hipStream_t>(stream)));
+  if (staged) {
+    // lambda_best, scores and info are per series in either layout
+    char* xs = static_cast<char*>(workspace);
+    uint8_t* ws8 = reinterpret_cast<uint8_t*>(xs + up256((size_t)((L.P + 63) / 64) * 64 * (size_t)L.T * e));
+    hipError_t err = whs::launch_interleave(x, xs, L.P, L.T, (int)e, true, s);
+    if (err == hipSuccess) err = whs::launch_interleave(w, ws8, L.P, L.T, 1, true, s);
+    if (err != hipSuccess) return hip_status(err);
+    L.S = 64;
+    L.x = xs;
+    L.w = ws8;
+  }
+  return hip_status(whs::launch_gcv(L, s));
 }
 
 size_t whs_variance_workspace_bytes(const whs_desc* desc) {
   if (check_desc(desc) != WHS_OK || desc->n_series == 0) return 0;
+  if (desc->interleave == 1) return staged_fits(desc) ? var_staged_bytes(desc) : 0;
   return whs::var_checkpoint_bytes(desc->n_series, desc->interleave, desc->T, desc->d);
 }
 
@@ -433,20 +476,44 @@ int whs_variance(const whs_desc* desc, const uint8_t* w, const void* lambda, voi
   if (st != WHS_OK) return st;
   if (desc->w_format == WHS_W_BITS) return WHS_ERR_UNSUPPORTED;
   if (desc->n_rhs != 1) return WHS_ERR_ARG;
-  if (desc->interleave % 64 != 0 || desc->n_series >= ((int64_t)1 << 31)) return WHS_ERR_UNSUPPORTED;
+  if ((desc->interleave % 64 != 0 && desc->interleave != 1) || desc->n_series >= ((int64_t)1 << 31))
+    return WHS_ERR_UNSUPPORTED;
   if (desc->n_series == 0) return WHS_OK;
   if (!w || !lambda || !var) return WHS_ERR_ARG;
   const size_t e = elem(desc);
   if (!aligned(lambda, e) || !aligned(var, e) || !aligned(info, 4)) return WHS_ERR_ARG;
+  const bool staged = desc->interleave == 1;
+  if (staged && !staged_fits(desc)) return WHS_ERR_UNSUPPORTED;
   if (!workspace || workspace_bytes < whs_variance_workspace_bytes(desc) || !aligned(workspace, 8))
     return WHS_ERR_WORKSPACE;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
   whs::LaunchDesc L = make_launch(desc);
   L.w = w;
   L.lam = lambda;
   L.out = var;
   L.info = info;
   L.ws = static_cast<double*>(workspace);
-  return hip_status(whs::launch_var(L, static_cast<hipStream_t>(stream)));
+  if (!staged) return hip_status(whs::launch_var(L, s));
+  // copies of w and lambda (per difference row) in, var out; a scalar lambda
+  // and info are per series in either layout
+  const size_t nb = (size_t)((L.P + 63) / 64);
+  const bool pd = desc->lambda_kind == WHS_LAMBDA_PER_DIFF;
+  char* p = static_cast<char*>(workspace);
+  uint8_t* wc = reinterpret_cast<uint8_t*>(p);
+  char* lc = (p += up256(nb * 64 * (size_t)L.T));
+  char* vc = (p += pd ? up256(nb * 64 * (size_t)(L.T - L.D) * e) : 0);
+  double* ck = reinterpret_cast<double*>(p += up256(nb * 64 * (size_t)L.T * e));
+  hipError_t err = whs::launch_interleave(w, wc, L.P, L.T, 1, true, s);
+  if (err == hipSuccess && pd) err = whs::launch_interleave(lambda, lc, L.P, L.T - L.D, (int)e, true, s);
+  if (err != hipSuccess) return hip_status(err);
+  L.S = 64;
+  L.w = wc;
+  L.lam = pd ? static_cast<const void*>(lc) : lambda;
+  L.out = vc;
+  L.ws = ck;
+  err = whs::launch_var(L, s);
+  if (err == hipSuccess) err = whs::launch_interleave(vc, var, L.P, L.T, (int)e, false, s);
+  return hip_status(err);
 }
 
 }  // extern "C"

@@ -144,6 +144,10 @@ def test_empty_batch_is_a_noop():
         assert L.whs_backward_coef(ctypes.byref(e), None, None, None, None, None, None, None, None, None, 0,
                                    None) == 0
         assert L.whs_interleave_workspace_bytes(ctypes.byref(e)) == 0
+        assert L.whs_gcv(ctypes.byref(e), None, None, None, 21, None, None, None, None, 0, None) == 0
+        assert L.whs_variance(ctypes.byref(e), None, None, None, None, None, 0, None) == 0
+        assert L.whs_gcv_workspace_bytes(ctypes.byref(e)) == 0
+        assert L.whs_variance_workspace_bytes(ctypes.byref(e)) == 0
     assert L.whs_solve_coef(ctypes.byref(whs.make_desc(0, 50, 2, 1, 32, 0, 0)), None, None, None, None, None,
                             None, None, 0, None) == -2                                  # layout still checked
     assert L.whs_gcv(ctypes.byref(desc), None, None, None, 21, None, None, None, None, 0, None) == 0
@@ -218,6 +222,17 @@ def test_gcv_validation():
     desc = whs.make_desc(10, 50, 2, 1, 64, 0, 0)
     assert L.whs_gcv(ctypes.byref(desc), FAKE, FAKE, g, 0, FAKE, None, None, FAKE, 1 << 30, None) == -1
     assert L.whs_gcv_workspace_bytes(ctypes.byref(desc)) == 0    # one forward sweep, no workspace
+    # interleave 1: copies of x and w; a smaller workspace is refused before any launch
+    up = lambda n: (n + 255) // 256 * 256   # noqa: E731
+    for dt, e in [(0, 4), (1, 8)]:
+        desc = whs.make_desc(70, 50, 2, 1, 1, dt, 0)
+        n = L.whs_gcv_workspace_bytes(ctypes.byref(desc))
+        assert n == up(128 * 50 * e) + up(128 * 50)
+        assert L.whs_gcv(ctypes.byref(desc), FAKE, FAKE, g, 21, FAKE, None, None, FAKE, n - 8, None) == -4
+        assert L.whs_gcv(ctypes.byref(desc), FAKE, FAKE, g, 21, FAKE, None, None, None, 0, None) == -4
+    huge = whs.make_desc(2 ** 30, 365, 2, 1, 1, 0, 0)
+    assert L.whs_gcv_workspace_bytes(ctypes.byref(huge)) == 0
+    assert L.whs_gcv(ctypes.byref(huge), FAKE, FAKE, g, 21, FAKE, None, None, FAKE, 1 << 40, None) == -2
 
 
 def test_plan_validation():
@@ -239,8 +254,21 @@ def test_variance_validation():
     L = whs.lib()
     desc = whs.make_desc(10, 50, 2, 2, 64, 0, 1)        # one output channel only
     assert L.whs_variance(ctypes.byref(desc), FAKE, FAKE, FAKE, None, FAKE, 1 << 30, None) == -1
-    desc = whs.make_desc(10, 50, 2, 1, 1, 0, 1)         # interleave not a multiple of 64
+    desc = whs.make_desc(10, 50, 2, 1, 32, 0, 1)        # interleave neither 1 nor a multiple of 64
     assert L.whs_variance(ctypes.byref(desc), FAKE, FAKE, FAKE, None, FAKE, 1 << 30, None) == -2
+    # interleave 1: copies of w, lambda (per difference row) and var, then the
+    # checkpoints of interleave 64; a smaller workspace is refused before any launch
+    up = lambda n: (n + 255) // 256 * 256   # noqa: E731
+    for kind, dt in [(1, 0), (0, 1)]:
+        desc = whs.make_desc(10, 50, 2, 1, 1, dt, kind)
+        e = 8 if dt else 4
+        n = L.whs_variance_workspace_bytes(ctypes.byref(desc))
+        assert n == up(64 * 50) + (up(64 * 48 * e) if kind else 0) + up(64 * 50 * e) + ((50 + 15) // 16) * 5 * 64 * 8
+        assert L.whs_variance(ctypes.byref(desc), FAKE, FAKE, FAKE, None, FAKE, n - 8, None) == -4
+        assert L.whs_variance(ctypes.byref(desc), FAKE, FAKE, FAKE, None, None, 0, None) == -4
+    huge = whs.make_desc(2 ** 30, 365, 2, 1, 1, 0, 1)   # the copies' grid does not fit a launch
+    assert L.whs_variance_workspace_bytes(ctypes.byref(huge)) == 0
+    assert L.whs_variance(ctypes.byref(huge), FAKE, FAKE, FAKE, None, FAKE, 1 << 40, None) == -2
     desc = whs.make_desc(10, 50, 2, 1, 64, 0, 1)
     assert L.whs_variance(ctypes.byref(desc), FAKE, None, FAKE, None, FAKE, 1 << 30, None) == -1
     assert L.whs_variance(ctypes.byref(desc), FAKE, FAKE, FAKE_ODD, None, FAKE, 1 << 30, None) == -1

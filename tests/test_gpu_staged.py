@@ -5,8 +5,8 @@ kernels on the same values), which the oracle parity of the interleaved path
 then covers: every order, several bands (beyond the partition kernel's one),
 both weight kinds, both storage types, the adjoint, a series count that is not
 a multiple of 64, the uneven-date calls, which take the contiguous layout
-only this way, and arrays and workspaces whose addresses make the copies take
-their narrower accesses."""
+only this way, GCV and the posterior variance, and arrays and workspaces whose
+addresses make the copies take their narrower accesses."""
 
 import ctypes
 
@@ -107,3 +107,35 @@ def test_contiguous_calls_at_unaligned_addresses(dt, k_x, k_w, ws_off):
     np.testing.assert_array_equal(from_device_series(zo, P), from_device_series(z64, P))
     np.testing.assert_array_equal(from_device_series(gxo, P), from_device_series(gx64, P))
     np.testing.assert_array_equal(from_device_rows(glo, P), from_device_rows(gl64, P))
+
+
+GCV_GRID = 10.0 ** (-1 + 0.3 * np.arange(21))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("P,T,d", [(70, 300, 2), (33, 350, 1), (130, 97, 3), (5, 40, 4)])
+def test_gcv_contiguous_matches_interleaved(P, T, d, dt):
+    dtype = DT[dt]
+    x, w, _ = random_case(P, T, d, per_diff=False, seed=P + T, dtype=dtype)
+    (x64, w64, _), (x1, w1, _) = both_layouts(x, w, np.ones(P), dtype)
+    grid = torch.tensor(GCV_GRID, device="cuda")
+    lb64, sc64, i64 = whs.whs_gcv(x64, w64, grid, d, P, want_scores=True)
+    lb1, sc1, i1 = whs.whs_gcv(x1, w1, grid, d, P, want_scores=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(i1.cpu().numpy(), i64.cpu().numpy())
+    np.testing.assert_array_equal(lb1.cpu().numpy(), lb64.cpu().numpy())
+    np.testing.assert_array_equal(sc1.cpu().numpy(), sc64.cpu().numpy())
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("per_diff", [True, False])
+@pytest.mark.parametrize("P,T,d", [(70, 300, 2), (33, 350, 1), (130, 97, 3), (5, 40, 4)])
+def test_variance_contiguous_matches_interleaved(P, T, d, per_diff, dt):
+    dtype = DT[dt]
+    x, w, lam = random_case(P, T, d, per_diff=per_diff, seed=2 * P + T, dtype=dtype)
+    (_, w64, l64), (_, w1, l1) = both_layouts(x, w, lam, dtype)
+    v64, i64 = whs.whs_variance(w64, l64, d, P)
+    v1, i1 = whs.whs_variance(w1, l1, d, P)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(i1.cpu().numpy(), i64.cpu().numpy())
+    np.testing.assert_array_equal(from_device_series(v1, P), from_device_series(v64, P))
