@@ -242,7 +242,8 @@ def bench_multiband(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"homoscedastic smoother {'fwd+bwd' if args.fwd_bwd else 'forward'}: P={P}, T={T}, "
                                f"d=2, C=10 bands sharing one factor, "
-                               f"scalar lambda, {args.dtype.upper()} storage / FP64 arithmetic",
+                               f"scalar lambda, {'FP64' if args.dtype == 'f64' else 'FP32'} storage / "
+                               f"FP64 arithmetic",
                    "P": P, "T": T, "d": d, "C": C, "storage": args.dtype},
         "roofline": {"bound": "hbm", "kernel": "whs_solve + whs_backward" if args.fwd_bwd else "whs_solve",
                      "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -337,13 +338,58 @@ def bench_gcv(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"plain form: GCV choice of a scalar weight over 21 grid values, then the solve at "
                                f"it: P={P} series, T={T} daily steps, d={d}, one band, "
-                               f"{args.dtype.upper()} storage / FP64 arithmetic",
+                               f"{'FP64' if args.dtype == 'f64' else 'FP32'} storage / FP64 arithmetic",
                    "P": P, "T": T, "d": d, "n_grid": grid.numel(), "storage": args.dtype, "interleave": S,
                    **({"contiguous_path": "interleaved copies"} if S == 1 else {})},
         "roofline": {"bound": "alu", "kernel": "whs_gcv", "achieved": tf, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": tf / PEAK_FP64_TFLOPS, "traffic": None,
                      "flops_per_series_step_grid_value": GCV_FLOPS_PER_STEP[d], "ms_per_launch": gcv_ms},
         "mean_log10_lambda": float(torch.log10(lam_best.double()).mean().item()),
+        "failed_series": int((info != 0).sum().item()),
+    }
+
+
+def bench_variance(args):
+    """Posterior variance diag(Omega^-1) of the heteroscedastic batch (0/1 weights,
+    a weight per difference row): the two sweeps without a right-hand side."""
+    import torch
+    from paper_2604_00048_amd import synth, whs
+    dev = torch.device("cuda:0")
+    f64 = args.dtype == "f64"
+    dt, esz = (torch.float64, 8) if f64 else (torch.float32, 4)
+    d, S, P, T = args.d, args.interleave, args.P, args.T
+    pk = synth.generate_packed("heteroscedastic", P, S=S, dtype=dt, device=dev, chunk=8192, T=T, d=d)
+    desc = whs.make_desc(P, T, d, 1, S, whs.WHS_F64 if f64 else whs.WHS_F32, whs.WHS_LAMBDA_PER_DIFF)
+    nws = int(whs.lib().whs_variance_workspace_bytes(ctypes.byref(desc)))
+    ws = torch.empty(max(nws, 8), dtype=torch.uint8, device=dev)
+    var = torch.empty_like(pk.x)
+    info = torch.empty(P, dtype=torch.int32, device=dev)
+
+    def step():
+        whs.whs_variance(pk.w, pk.lam, d, P, var=var, info=info, workspace=ws)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = _events(2)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    alg = T + esz * (T - d) + esz * T      # w, lambda, var: each once
+    gbs = alg * P / (ms * 1e-3) / 1e9
+    return {
+        "metric": f"series/sec (posterior variance, T={T}, d={d})", "value": P / (ms * 1e-3),
+        "unit": "series/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"posterior variance diag(Omega^-1): P={P} series, T={T} daily steps, d={d}, "
+                               f"per-difference lambda (log10 GP field), {'FP64' if f64 else 'FP32'} storage / "
+                               f"FP64 arithmetic", "P": P, "T": T, "d": d, "storage": args.dtype, "interleave": S,
+                   **({"contiguous_path": "interleaved copies"} if S == 1 else {})},
+        "roofline": {"bound": "hbm", "kernel": "whs_variance", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None, "alg_bytes_per_series": alg,
+                     "ms_per_launch": ms},
         "failed_series": int((info != 0).sum().item()),
     }
 
@@ -411,7 +457,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="hetero", choices=["hetero", "multiband", "uneven", "learned", "transformer", "gcv"])
+    ap.add_argument("--workload", default="hetero", choices=["hetero", "multiband", "uneven", "learned", "transformer", "gcv", "variance"])
     ap.add_argument("--P", type=int, default=None)
     ap.add_argument("--T", type=int, default=3288)
     ap.add_argument("--d", type=int, default=2, help="difference order of the heteroscedastic workload")
@@ -480,6 +526,10 @@ def main():
     if args.workload == "gcv":
         args.P = args.P or 262144
         print(json.dumps(bench_gcv(args)), flush=True)
+        return
+    if args.workload == "variance":
+        args.P = args.P or 65536
+        print(json.dumps(bench_variance(args)), flush=True)
         return
     if args.workload == "learned":
         args.eval_series = args.eval_series or 262144
