@@ -394,6 +394,85 @@ def bench_variance(args):
     }
 
 
+def bench_uneven_dates(args):
+    """Forward solve + adjoint on irregular acquisition dates (the divided-difference
+    D of the real dates, through its coefficient table): P series sharing --acq dates,
+    --bands bands each, a weight per difference row, FP32 storage."""
+    import torch
+    from paper_2604_00048_amd import synth, whs
+    dev = torch.device("cuda:0")
+    P, T, C, d = args.P, args.acq, args.bands, args.d
+    S, n = 64, 8192
+    if P % n:
+        raise SystemExit(f"--P must be a multiple of {n} for this workload")
+    gen = torch.Generator(device=dev).manual_seed(23)
+    days = synth.acquisition_days(T, gen, dev)
+    coef = whs.whs_diff_coef(days.contiguous(), d)
+    nb = P // S
+    x = torch.empty((nb, T, C, S), dtype=torch.float32, device=dev)
+    w = torch.empty((nb, T, S), dtype=torch.uint8, device=dev)
+    for k in range(P // n):
+        _, b = synth.irregular_sits(n, T, C, 29, dev, chunk=k, days=days)
+        x[k * n // S:(k + 1) * n // S] = synth.pack_series(b.x.float(), S)
+        w[k * n // S:(k + 1) * n // S] = synth.pack_rows(b.w, S)
+        del b
+    # log10 of the weight per difference row: uniform on [1, 4]
+    lam = torch.pow(10.0, 1.0 + 3.0 * torch.rand((nb, T - d, S), generator=gen, device=dev)).float()
+    g = torch.randn(x.shape, generator=gen, device=dev, dtype=torch.float32)
+    z, gx, gl = torch.empty_like(x), torch.empty_like(x), torch.empty_like(lam)
+    info = torch.empty(P, dtype=torch.int32, device=dev)
+    desc = whs.make_desc(P, T, d, C, S, whs.WHS_F32, whs.WHS_LAMBDA_PER_DIFF)
+    ws = torch.empty(max(whs.workspace_bytes(desc), 8), dtype=torch.uint8, device=dev)
+
+    def solve():
+        whs.whs_solve(x, w, lam, d, P, z=z, info=info, workspace=ws, coef=coef)
+
+    def adjoint():
+        whs.whs_backward(w, lam, z, g, d, P, grad_x=gx, grad_lambda=gl, info=info, workspace=ws, coef=coef)
+    for _ in range(args.warmup):
+        solve()
+        adjoint()
+    torch.cuda.synchronize()
+    K = args.steps
+    ev = [_events(3) for _ in range(K)]
+    e0, e1 = _events(2)
+    e0.record()
+    for k in range(K):
+        ev[k][0].record()
+        solve()
+        ev[k][1].record()
+        adjoint()
+        ev[k][2].record()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / K
+    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    bwd_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+    fb, bb = alg_bytes(T, d, C, 4, True)
+    fwd_gbs, bwd_gbs = fb * P / (fwd_ms * 1e-3) / 1e9, bb * P / (bwd_ms * 1e-3) / 1e9
+    step_gbs = (fb + bb) * P / (ms * 1e-3) / 1e9
+    return {
+        "metric": f"series/sec (uneven dates, T={T} acquisitions, C={C} bands, d={d}, fwd+bwd)",
+        "value": P / (ms * 1e-3), "unit": "series/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"smoother fwd+bwd on irregular acquisition dates: P={P} series sharing T={T} "
+                               f"dates over 3288 days, C={C} bands (double-logistic phenology, Bernoulli validity "
+                               f"masks), d={d}, per-difference lambda, FP32 storage / FP64 arithmetic",
+                   "P": P, "T": T, "C": C, "d": d, "storage": "f32", "interleave": S},
+        "roofline": {"bound": "hbm", "kernel": "whs_backward_coef", "achieved": bwd_gbs, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": bwd_gbs / PEAK_HBM_GBS, "traffic": None, "alg_bytes_per_series": bb,
+                     "ms_per_launch": bwd_ms},
+        "kernels": {
+            "whs_solve_coef": {"ms": fwd_ms, "alg_GBps": fwd_gbs, "frac": fwd_gbs / PEAK_HBM_GBS,
+                               "alg_bytes_per_series": fb},
+            "whs_backward_coef": {"ms": bwd_ms, "alg_GBps": bwd_gbs, "frac": bwd_gbs / PEAK_HBM_GBS},
+            "step": {"ms": ms, "alg_GBps": step_gbs, "frac": step_gbs / PEAK_HBM_GBS},
+        },
+        "failed_series": int((info != 0).sum().item()),
+    }
+
+
 def bench_learned(args):
     """Learned per-day weights vs the GCV-chosen scalar weight, held-out RMSE and throughput."""
     import torch
@@ -457,7 +536,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="hetero", choices=["hetero", "multiband", "uneven", "learned", "transformer", "gcv", "variance"])
+    ap.add_argument("--workload", default="hetero",
+                    choices=["hetero", "multiband", "uneven", "learned", "transformer", "gcv", "variance",
+                             "uneven_dates"])
     ap.add_argument("--P", type=int, default=None)
     ap.add_argument("--T", type=int, default=3288)
     ap.add_argument("--d", type=int, default=2, help="difference order of the heteroscedastic workload")
@@ -526,6 +607,10 @@ def main():
     if args.workload == "gcv":
         args.P = args.P or 262144
         print(json.dumps(bench_gcv(args)), flush=True)
+        return
+    if args.workload == "uneven_dates":
+        args.P = args.P or 262144
+        print(json.dumps(bench_uneven_dates(args)), flush=True)
         return
     if args.workload == "variance":
         args.P = args.P or 65536

@@ -283,14 +283,19 @@ def acquisition_days(T: int, gen, device, revisit: int = 5, n_days: int = 3288) 
     return (pick * revisit + 1).to(torch.float64)
 
 
-def irregular_sits(P: int, T: int, C: int, seed: int, device, chunk: int = 0, p_valid=(0.3, 0.8)):
+def irregular_sits(P: int, T: int, C: int, seed: int, device, chunk: int = 0, p_valid=(0.3, 0.8), days=None):
     """Irregular multi-band series: ``P`` pixels sharing ``T`` acquisition days,
     double-logistic bands sampled at those days with N(0, 0.02) noise, and a
     per-pixel validity mask ``w ~ Bernoulli(p)``, ``p ~ U[p_valid]`` (the
     masks a cloud detector provides).  Returns ``(days, Batch)``, the batch in
-    natural layout with ``x`` zero where ``w`` is 0."""
+    natural layout with ``x`` zero where ``w`` is 0.  ``days``: the acquisition
+    days to use (ascending, within the 3288-day span) instead of drawing them,
+    so that chunks of one batch share their dates."""
     gen = _gen(seed * 1_000_003 + chunk, device)
-    days = acquisition_days(T, gen, device)
+    if days is None:
+        days = acquisition_days(T, gen, device)
+    elif days.numel() != T:
+        raise ValueError(f"days must hold T={T} values")
     x_day, clean_day = phenology(P, 3288, C, gen, device)
     idx = days.long()
     x = x_day[:, idx, :].contiguous()
