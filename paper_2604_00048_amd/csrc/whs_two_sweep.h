@@ -430,12 +430,14 @@ constexpr int tile_depth() {
 // The fast solve of 2 or 3 bands in FP32 storage (order <= 2, even times) has
 // room for 16 steps: two bands with either weight kind, three with one weight
 // per series.  With uneven times, one band takes 16 steps (order <= 2) or 12
-// except in the adjoint with a weight per difference row.  Never shallower
-// than tile_depth, which sizes the checkpoints.
+// except in the adjoint with a weight per difference row, and the solve of a
+// 4-band group in FP32 (order <= 2) 12.  Never shallower than tile_depth,
+// which sizes the checkpoints.
 template <int D, int C, bool TAB, int ES, bool BWD, bool PERDIFF>
 constexpr int fast_tile_depth() {
   if (!TAB && !BWD && ES == 4 && D <= 2 && (C == 2 || (C == 3 && !PERDIFF))) return 16;
   if (TAB && C == 1 && !(BWD && PERDIFF)) return D <= 2 ? 16 : 12;
+  if (TAB && C == 4 && !BWD && ES == 4 && D <= 2) return 12;
   return tile_depth<D, C, TAB, ES>();
 }
 
@@ -646,10 +648,16 @@ hipError_t run_groups_tab(const LaunchDesc& L, hipStream_t stream) {
     const int wi = c0 == 0;
     hipError_t e;
     if (g == 4) {
-      e = launch_fast<D, 4, TS, Src::Fused, MODE, PERDIFF, true>(L, c0, wi, stream);
+      // the adjoint takes 4 bands only where tab_max_group allows them
+      if constexpr (!kBwd || (D <= 2 && sizeof(TS) == 4 && PERDIFF))
+        e = launch_fast<D, 4, TS, Src::Fused, MODE, PERDIFF, true>(L, c0, wi, stream);
+      else e = hipErrorInvalidValue;  // never chosen
     } else if (g == 2) {
-      if constexpr (kBwd) e = launch_fast<D, 2, TS, Src::Fused, MODE, PERDIFF, true>(L, c0, wi, stream);
-      else e = hipErrorInvalidValue;  // never chosen for the solve
+      // 2 bands: the adjoint only, where tab_max_group allows at least 2
+      constexpr bool kF64 = sizeof(TS) == 8;
+      if constexpr (kBwd && (D <= 2 || (D == 3 && !(kF64 && !PERDIFF)) || (D == 4 && PERDIFF)))
+        e = launch_fast<D, 2, TS, Src::Fused, MODE, PERDIFF, true>(L, c0, wi, stream);
+      else e = hipErrorInvalidValue;  // never chosen
     } else {
       e = launch_fast<D, 1, TS, Src::Fused, MODE, PERDIFF, true>(L, c0, wi, stream);
     }
