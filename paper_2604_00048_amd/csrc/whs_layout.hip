@@ -138,26 +138,34 @@ __device__ inline void transpose_bytes(const uint32_t a[4], uint32_t o[4]) {
 }
 
 // 1-byte elements, a tile of 64 series x 256 steps held in LDS as 4-step words
-// of each series.  The series-contiguous side is read or written a word per lane
-// (64 lanes cover a series' 256 steps; L % 4 == 0), the interleaved side 16 bytes
-// per lane (16 series of one step); each lane turns four 4-series x 4-step byte
-// squares around in registers between the two.
+// of each series.  The series-contiguous side is read or written W words per
+// lane (64 / W lanes cover a series' 256 steps; L % (4 W) == 0), the
+// interleaved side 16 bytes per lane (16 series of one step); each lane turns
+// four 4-series x 4-step byte squares around in registers between the two.
+template <int W>
 __global__ __launch_bounds__(256) void k_interleave1(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst,
                                                      int64_t P, int64_t L, int to_interleaved, int64_t ny) {
-  __shared__ uint32_t tile[64 * 65];  // [series][4-step word], pitch 65 words
+  using vec = uint32_t __attribute__((ext_vector_type(W)));
+  constexpr int kLanes = 64 / W;        // lanes per series row on the contiguous side (W words each)
+  constexpr int kRows = 256 / kLanes;   // series rows per pass there
+  __shared__ uint32_t tile[64 * 65];    // [series][4-step word], pitch 65 words
   int64_t b, by;
   if (!xcd_tile(ny, ny * ((P + 63) / 64), b, by)) return;
   const int64_t j0 = by * 256;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int h = t & 3, cw = t >> 2;  // interleaved side: 16-series group, 4-step word of the tile
-  const int64_t Lw = L / 4, jw = j0 / 4 + lane;
+  const int t = threadIdx.x;
+  const int c = t % kLanes, r0 = t / kLanes;  // contiguous side: W-word column, first series
+  const int h = t & 3, cw = t >> 2;           // interleaved side: 16-series group, 4-step word of the tile
+  const int64_t Lw = L / 4, jw = j0 / 4 + W * c;
   if (to_interleaved) {
     const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int r = wv * 16 + i;
+    for (int i = 0; i < 64 / kRows; ++i) {
+      const int r = r0 + kRows * i;
       const int64_t p = b * 64 + r;
-      tile[r * 65 + lane] = (p < P && jw < Lw) ? s[p * Lw + jw] : 0u;
+      vec v = vec(0u);
+      if (p < P && jw < Lw) v = *reinterpret_cast<const vec*>(s + p * Lw + jw);
+#pragma unroll
+      for (int e = 0; e < W; ++e) tile[r * 65 + W * c + e] = v[e];
     }
     __syncthreads();
     uint32_t o[4][4];  // [step k][series quad e]
@@ -173,7 +181,8 @@ __global__ __launch_bounds__(256) void k_interleave1(const uint8_t* __restrict__
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int64_t j = j0 + 4 * cw + k;
-      if (j < L) *reinterpret_cast<uint4*>(dst + (b * L + j) * 64 + 16 * h) = make_uint4(o[k][0], o[k][1], o[k][2], o[k][3]);
+      if (j < L)
+        *reinterpret_cast<uint4*>(dst + (b * L + j) * 64 + 16 * h) = make_uint4(o[k][0], o[k][1], o[k][2], o[k][3]);
     }
   } else {
     uint32_t in[4][4];  // [step k][series quad e]
@@ -199,10 +208,15 @@ __global__ __launch_bounds__(256) void k_interleave1(const uint8_t* __restrict__
     __syncthreads();
     uint32_t* d = reinterpret_cast<uint32_t*>(dst);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int r = wv * 16 + i;
+    for (int i = 0; i < 64 / kRows; ++i) {
+      const int r = r0 + kRows * i;
       const int64_t p = b * 64 + r;
-      if (p < P && jw < Lw) d[p * Lw + jw] = tile[r * 65 + lane];
+      if (p < P && jw < Lw) {
+        vec v;
+#pragma unroll
+        for (int e = 0; e < W; ++e) v[e] = tile[r * 65 + W * c + e];
+        *reinterpret_cast<vec*>(d + p * Lw + jw) = v;
+      }
     }
   }
 }
@@ -240,9 +254,12 @@ hipError_t launch_interleave(const void* src, void* dst, int64_t P, int64_t L, i
   switch (elem_bytes) {
     case 1:
       n = grid1(256, ny);
-      if (n <= kMaxGroups && L % 4 == 0 && ac % 4 == 0 && ai % 16 == 0) {
-        hipLaunchKernelGGL(k_interleave1, dim3((unsigned)n), dim3(256), 0, stream, static_cast<const uint8_t*>(src),
-                           static_cast<uint8_t*>(dst), P, L, dir, ny);
+      if (n <= kMaxGroups && L % 8 == 0 && ac % 8 == 0 && ai % 16 == 0) {
+        hipLaunchKernelGGL(k_interleave1<2>, dim3((unsigned)n), dim3(256), 0, stream,
+                           static_cast<const uint8_t*>(src), static_cast<uint8_t*>(dst), P, L, dir, ny);
+      } else if (n <= kMaxGroups && L % 4 == 0 && ac % 4 == 0 && ai % 16 == 0) {
+        hipLaunchKernelGGL(k_interleave1<1>, dim3((unsigned)n), dim3(256), 0, stream,
+                           static_cast<const uint8_t*>(src), static_cast<uint8_t*>(dst), P, L, dir, ny);
       } else if (narrow_fits) {
         hipLaunchKernelGGL(k_interleave<uint8_t>, grid, dim3(256), 0, stream, static_cast<const uint8_t*>(src),
                            static_cast<uint8_t*>(dst), P, L, dir);
